@@ -1,0 +1,129 @@
+"""CPU oracle for MT4G's K-S change-point detection (arXiv 2511.05958).
+
+TEST INFRASTRUCTURE: a slow, plain restatement of the method that the GPU
+path is checked against. Only ``tests/``, ``__graft_entry__.smoke()`` and
+``bench.py``'s ``cpu_baseline`` leg may import it. It shares no code with the
+HIP path; the product never imports it.
+
+The arithmetic lives in ``ks_oracle.c`` (exact integers, long double for the
+p-value); this module is ctypes marshalling plus numpy views. Each function
+cites the passage it restates:
+
+* ``reduce``         eq. 2 (Section "Size benchmarks", workflow step 4)
+* ``split_U``        the two-sample K-S statistic, D = max_x |F(x) - G(x)|,
+                     lower side vs higher side of a candidate (Section
+                     "Background", K-S test)
+* ``scan_series``    every index a candidate, the most significant one chosen,
+                     eq. 1 significance, p-value as confidence (workflow step 4)
+* ``kolmogorov``     the asymptotic distribution behind eq. 1
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from pathlib import Path
+
+import numpy as np
+
+_LIB_PATH = Path(__file__).resolve().parent / "libks_oracle.so"
+
+RESULT_DTYPE = np.dtype(
+    [("cp", "<u4"), ("n", "<u4"), ("m", "<u4"), ("U", "<u4"), ("D", "<f8"), ("lambda", "<f8"),
+     ("p", "<f8"), ("significant", "<u4"), ("status", "<u4")]
+)
+assert RESULT_DTYPE.itemsize == 48
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not _LIB_PATH.exists():
+            from . import build as _b  # noqa: F401  (oracle/build.py)
+
+            _b.build()
+        lib = ctypes.CDLL(str(_LIB_PATH))
+        vp = ctypes.c_void_p
+        u32 = ctypes.c_uint32
+        lib.oracle_reduce.argtypes = [vp, u32, u32, vp, vp, vp]
+        lib.oracle_reduce.restype = None
+        lib.oracle_split_U.argtypes = [vp, vp, u32, u32]
+        lib.oracle_split_U.restype = ctypes.c_uint64
+        lib.oracle_c_alpha.argtypes = [ctypes.c_double]
+        lib.oracle_c_alpha.restype = ctypes.c_double
+        lib.oracle_kolmogorov.argtypes = [ctypes.c_double]
+        lib.oracle_kolmogorov.restype = ctypes.c_double
+        lib.oracle_scan_series.argtypes = [vp, u32, u32, ctypes.c_double, vp, vp]
+        lib.oracle_scan_batch.argtypes = [vp, vp, vp, vp, u32, ctypes.c_double, vp, vp, vp, ctypes.c_int]
+        assert lib.oracle_result_size() == 48
+        _lib = lib
+    return _lib
+
+
+def _u32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+def reduce(r) -> tuple[int, list[int]]:
+    """Eq. 2 squared: (global min, [Q_0..Q_{K-1}]) with Q_i = sum_j (r_ij - min)^2 exact."""
+    r = _u32(r)
+    K, N = r.shape
+    lo = np.zeros(K, np.uint64)
+    hi = np.zeros(K, np.uint64)
+    mn = ctypes.c_uint32(0)
+    _load().oracle_reduce(r.ctypes.data, K, N, ctypes.byref(mn), lo.ctypes.data, hi.ctypes.data)
+    return int(mn.value), [(int(h) << 64) | int(l) for l, h in zip(lo, hi)]
+
+
+def split_U(Q, c: int) -> int:
+    """U_c = n m D_c for the split lower = Q[:c], higher = Q[c:]."""
+    K = len(Q)
+    lo = np.array([q & ((1 << 64) - 1) for q in Q], np.uint64)
+    hi = np.array([q >> 64 for q in Q], np.uint64)
+    return int(_load().oracle_split_U(lo.ctypes.data, hi.ctypes.data, K, c))
+
+
+def c_alpha(alpha: float) -> float:
+    """Eq. 1 constant: d_alpha^2 = c_alpha (n+m)/(n m), c_alpha = -1/2 ln(alpha/2)."""
+    return float(_load().oracle_c_alpha(alpha))
+
+
+def kolmogorov(lambda2: float) -> float:
+    """Asymptotic Kolmogorov tail Q_KS(lambda) from lambda^2."""
+    return float(_load().oracle_kolmogorov(lambda2))
+
+
+def scan_series(r, alpha: float = 0.05, want_allU: bool = False):
+    """Full detection on one [K][N] series. Returns a RESULT_DTYPE record (and U_c for c<K)."""
+    r = _u32(r)
+    K, N = r.shape
+    res = np.zeros((), RESULT_DTYPE)
+    allU = np.zeros(max(K, 1), np.uint32)
+    _load().oracle_scan_series(r.ctypes.data, K, N, alpha, res.ctypes.data, allU.ctypes.data)
+    return (res, allU) if want_allU else res
+
+
+def scan_batch(samples, offsets, Ks, Ns, alpha: float = 0.05, threads: int | None = None,
+               want_allU: bool = False):
+    """Detection on many series of one packed buffer; series t is samples[offsets[t]:][:K*N]."""
+    samples = _u32(samples)
+    offsets = np.ascontiguousarray(offsets, np.uint64)
+    Ks = _u32(Ks)
+    Ns = _u32(Ns)
+    num = len(Ks)
+    if threads is None:
+        threads = os.cpu_count() or 1
+    res = np.zeros(num, RESULT_DTYPE)
+    if want_allU:
+        aoff = np.zeros(num, np.uint64)
+        if num:
+            aoff[1:] = np.cumsum(Ks.astype(np.uint64))[:-1]
+        allU = np.zeros(int(Ks.astype(np.uint64).sum()), np.uint32)
+        _load().oracle_scan_batch(samples.ctypes.data, offsets.ctypes.data, Ks.ctypes.data, Ns.ctypes.data,
+                                  num, alpha, res.ctypes.data, allU.ctypes.data, aoff.ctypes.data, threads)
+        return res, allU, aoff
+    _load().oracle_scan_batch(samples.ctypes.data, offsets.ctypes.data, Ks.ctypes.data, Ns.ctypes.data,
+                              num, alpha, res.ctypes.data, None, None, threads)
+    return res
