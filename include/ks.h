@@ -1,0 +1,161 @@
+/*
+ * ks.h - C ABI of the MI355X (gfx950) Kolmogorov-Smirnov change-point library.
+ *
+ * The library detects the change point of latency-versus-footprint sweeps the
+ * way MT4G does (arXiv 2511.05958, Section "Benchmarks and Autoevaluation",
+ * size benchmarks, workflow step 4 "The K-S test"):
+ *
+ *   one series   = the 2-D timing array of one size sweep: K array sizes
+ *                  (rows) x the first N load latencies of each size
+ *                  (columns), uint32 cycles, row-major;
+ *   reduction    = eq. 2, S_i = sqrt(sum_j (r_ij - min r)^2), min r over the
+ *                  whole array; kept exactly as Q_i = S_i^2 (K-S needs ranks
+ *                  only, and sqrt is strictly increasing);
+ *   candidates   = every row index c in [1, K-1]; lower side rows [0, c)
+ *                  (n = c values), higher side rows [c, K) (m = K - c values);
+ *   statistic    = two-sample K-S, D_c = max_x |F(x) - G(x)| (Section
+ *                  "Background", K-S test), kept as the integer
+ *                  U_c = n m D_c = max |i m - j n| over complete tie groups;
+ *   choice       = the most significant candidate: largest
+ *                  lambda_c = D_c sqrt(n m / (n + m)), ties to the smaller c;
+ *   significance = eq. 1 with the sign fixed, d_alpha^2 = c_alpha (n+m)/(n m),
+ *                  c_alpha = -1/2 ln(alpha/2); H0 denied iff D > d_alpha,
+ *                  evaluated as U^2 > c_alpha n m K in IEEE double;
+ *   confidence   = asymptotic Kolmogorov p-value Q_KS(lambda) of the winner.
+ *
+ * Conventions for every entry point:
+ *   - Status: KS_OK (0) or a negative KS_E_* code; ks_status_string() names it.
+ *     A KS_E_HIP return keeps the HIP error text of the calling thread for
+ *     ks_status_string(KS_E_HIP).
+ *   - Memory: arguments documented as "device" are device pointers owned by
+ *     the caller; the library never frees or retains them past the call's
+ *     stream work. "host" arguments are read during the call only.
+ *   - Streams: `stream` is a hipStream_t of the context's device (NULL = the
+ *     null stream). Calls are asynchronous and stream-ordered; results are
+ *     valid once the stream's work up to the call has completed.
+ *   - Contexts are not thread-safe: use one ks_ctx per host thread.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KS_VERSION 10000 /* 1.0.0 */
+
+#define KS_MAX_K 2048u          /* rows per series */
+#define KS_MAX_N (1u << 24)     /* samples per row */
+
+/* status codes */
+#define KS_OK 0
+#define KS_E_INVALID (-1) /* null pointer, bad parameter */
+#define KS_E_RANGE (-2)   /* a size outside the documented limits */
+#define KS_E_STATE (-3)   /* call order / workspace stamp mismatch */
+#define KS_E_HIP (-4)     /* a HIP runtime call failed */
+#define KS_E_MODEL (-5)   /* bad model handle, file or weights */
+#define KS_E_NOMEM (-6)   /* device allocation failed */
+
+/* ks_result.flags */
+#define KS_SIGNIFICANT 1u    /* H0 denied at alpha (eq. 1) */
+#define KS_REFINED 2u        /* ks_refine: exact scan inside the +-w window */
+#define KS_FALLBACK 4u       /* ks_refine: low confidence, full exact scan */
+#define KS_BAD_SHAPE 8u      /* K < 2, K > max_K, N < 1 or N > KS_MAX_N; cp = 0 */
+#define KS_OUT_OF_RANGE 16u  /* offset + K*N exceeds num_samples; cp = 0 */
+
+/* One series of the batch. 24 bytes; an array of these lives in device memory.
+ *   offset      first sample of the series, in uint32 elements from `samples`
+ *   K, N        rows and samples per row; the series is samples[offset + i*N + j]
+ *   aux_offset  first slot of this series in the optional per-row outputs
+ *               (all_U), normally the sum of K over the preceding series */
+typedef struct ks_desc {
+  uint64_t offset;
+  uint32_t K;
+  uint32_t N;
+  uint64_t aux_offset;
+} ks_desc;
+
+/* Result of one series. 48 bytes.
+ *   cp      c*, the first row of the higher side (the change point); the
+ *           cache size lies between footprint[cp-1] and footprint[cp]
+ *   n, m    side sizes c* and K - c*
+ *   U       D numerator n m D (exact integer)
+ *   D       U / (n m)
+ *   lambda  sqrt(U^2 / (n m K))
+ *   p       asymptotic Kolmogorov p-value of lambda (FP64); 1 when U = 0,
+ *           0 when 2 lambda^2 > 700
+ *   flags   KS_* flags above */
+typedef struct ks_result {
+  uint32_t cp, n, m, U;
+  double D, lambda, p;
+  uint32_t flags, pad;
+} ks_result;
+
+/* Method and launch parameters. 32 bytes.
+ *   alpha    significance level in (0, 1)
+ *   c_alpha  -1/2 ln(alpha/2), filled by ks_params_init on the host so every
+ *            decision uses the same bits
+ *   max_K    upper bound on K over the batch (2..KS_MAX_K, 0 = KS_MAX_K);
+ *            sizes the per-workgroup LDS; series with K > max_K get
+ *            KS_BAD_SHAPE
+ *   w        refine half-window (ks_refine), 1..64, default 8
+ *   tau      confidence threshold of ks_refine in [0, 1]; below it the full
+ *            scan runs (default 0.5)
+ *   opts     reserved, must be 0 */
+typedef struct ks_params {
+  double alpha;
+  double c_alpha;
+  uint32_t max_K;
+  uint32_t w;
+  float tau;
+  uint32_t opts;
+} ks_params;
+
+typedef struct ks_ctx ks_ctx;
+
+/* KS_VERSION of the built library. */
+int ks_version(void);
+
+/* Static text for a status code (for KS_E_HIP, the calling thread's last HIP
+ * error text). Never NULL. */
+const char *ks_status_string(int status);
+
+/* Fill *p with alpha, c_alpha = -1/2 ln(alpha/2) (eq. 1 with the sign
+ * fixed), max_K = 0, w = 8, tau = 0.5, opts = 0. KS_E_INVALID if p is NULL
+ * or alpha is not in (0, 1). */
+int ks_params_init(ks_params *p, double alpha);
+
+/* Create a context on HIP device `device`: device properties, workspace,
+ * graph cache and tuning table. *out owns them until ks_ctx_destroy. */
+int ks_ctx_create(int device, ks_ctx **out);
+int ks_ctx_destroy(ks_ctx *ctx);
+
+/* Pre-allocate workspace for batches of up to max_series series and
+ * max_total_steps total rows, so that later calls of that size allocate
+ * nothing. Optional; calls grow the workspace on demand otherwise. */
+int ks_reserve(ks_ctx *ctx, uint32_t max_series, uint64_t max_total_steps);
+
+/* Exact scan of a batch (eq. 2 reduction, K-S at every candidate, choice,
+ * significance, p-value) for every series.
+ *   samples      device, uint32[num_samples]
+ *   desc         device, ks_desc[num_series]
+ *   params       host, read during the call
+ *   out          device, ks_result[num_series]
+ *   all_U        device, nullable: uint32[all_U_len]; series s writes
+ *                all_U[aux_offset + c] = U_c for c in [0, K) (U_0 = 0) when
+ *                aux_offset + K <= all_U_len, and nothing otherwise
+ * num_series == 0 is a no-op. Per-series shape or range errors are reported
+ * in out[s].flags (cp = 0), not as a status. KS_E_INVALID on a NULL pointer
+ * or a bad alpha / c_alpha / w / tau / opts, KS_E_RANGE on max_K outside
+ * [2, KS_MAX_K] (0 allowed). */
+int ks_scan_batch(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, const ks_desc *desc,
+                  uint32_t num_series, const ks_params *params, ks_result *out, uint32_t *all_U,
+                  uint64_t all_U_len, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KS_H */

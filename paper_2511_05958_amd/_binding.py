@@ -1,0 +1,229 @@
+"""ctypes binding of libks.so: the C ABI of include/ks.h, same names, marshalling only.
+
+Device buffers are passed as torch CUDA tensors (their data_ptr) or raw
+integer addresses; streams as torch.cuda.Stream, a raw hipStream_t address,
+or None for torch's current stream. Every step of the computation runs in the
+library's HIP kernels; if libks.so is missing, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+_LIB_PATH = Path(__file__).resolve().parent / "libks.so"
+
+KS_VERSION = 10000
+KS_MAX_K = 2048
+KS_MAX_N = 1 << 24
+
+KS_OK = 0
+KS_E_INVALID = -1
+KS_E_RANGE = -2
+KS_E_STATE = -3
+KS_E_HIP = -4
+KS_E_MODEL = -5
+KS_E_NOMEM = -6
+
+KS_SIGNIFICANT = 1
+KS_REFINED = 2
+KS_FALLBACK = 4
+KS_BAD_SHAPE = 8
+KS_OUT_OF_RANGE = 16
+
+DESC_DTYPE = np.dtype([("offset", "<u8"), ("K", "<u4"), ("N", "<u4"), ("aux_offset", "<u8")])
+RESULT_DTYPE = np.dtype(
+    [("cp", "<u4"), ("n", "<u4"), ("m", "<u4"), ("U", "<u4"), ("D", "<f8"), ("lambda", "<f8"),
+     ("p", "<f8"), ("flags", "<u4"), ("pad", "<u4")]
+)
+assert DESC_DTYPE.itemsize == 24 and RESULT_DTYPE.itemsize == 48
+
+
+class ks_params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("c_alpha", ctypes.c_double), ("max_K", ctypes.c_uint32),
+                ("w", ctypes.c_uint32), ("tau", ctypes.c_float), ("opts", ctypes.c_uint32)]
+
+
+assert ctypes.sizeof(ks_params) == 32
+
+
+class KsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {ks_status_string(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+
+_SIGNATURES = {
+    "ks_version": ([], ctypes.c_int),
+    "ks_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "ks_params_init": ([_vp, ctypes.c_double], ctypes.c_int),
+    "ks_ctx_create": ([ctypes.c_int, _vp], ctypes.c_int),
+    "ks_ctx_destroy": ([_vp], ctypes.c_int),
+    "ks_reserve": ([_vp, _u32, _u64], ctypes.c_int),
+    "ks_scan_batch": ([_vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp, _u64, _vp], ctypes.c_int),
+}
+
+
+def lib():
+    """The loaded libks.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not _LIB_PATH.exists():
+            raise RuntimeError(f"{_LIB_PATH} is missing: the HIP library must be built (__graft_entry__.build())")
+        so = ctypes.CDLL(str(_LIB_PATH))
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(so, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = so
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    return list(_SIGNATURES)
+
+
+def _check(code: int, what: str) -> None:
+    if code != KS_OK:
+        raise KsError(code, what)
+
+
+def _addr(x, nbytes_min: int | None = None, what: str = "buffer") -> int | None:
+    """Device address of a torch tensor / int / None, with a host-side size check."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if not x.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not x.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if nbytes_min is not None and x.numel() * x.element_size() < nbytes_min:
+        raise ValueError(f"{what} holds {x.numel() * x.element_size()} bytes, needs {nbytes_min}")
+    return x.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------- C ABI
+
+
+def ks_version() -> int:
+    return int(lib().ks_version())
+
+
+def ks_status_string(code: int) -> str:
+    return lib().ks_status_string(code).decode()
+
+
+def ks_params_init(alpha: float = 0.05) -> ks_params:
+    p = ks_params()
+    _check(lib().ks_params_init(ctypes.byref(p), alpha), "ks_params_init")
+    return p
+
+
+def ks_ctx_create(device: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().ks_ctx_create(device, ctypes.byref(h)), "ks_ctx_create")
+    return h
+
+
+def ks_ctx_destroy(ctx) -> None:
+    _check(lib().ks_ctx_destroy(ctx), "ks_ctx_destroy")
+
+
+def ks_reserve(ctx, max_series: int, max_total_steps: int) -> None:
+    _check(lib().ks_reserve(ctx, max_series, max_total_steps), "ks_reserve")
+
+
+def ks_scan_batch(ctx, samples, desc, num_series: int, params: ks_params, out, all_U=None, stream=None,
+                  num_samples: int | None = None) -> None:
+    """Exact scan of num_series series. samples: uint32 device buffer (int32/uint32 tensor);
+    desc: ks_desc[num_series] device buffer; out: ks_result[num_series] device buffer;
+    all_U: optional uint32 device buffer for every U_c."""
+    if num_samples is None:
+        num_samples = samples.numel() * samples.element_size() // 4
+    all_U_len = 0 if all_U is None else (all_U.numel() * all_U.element_size() // 4)
+    rc = lib().ks_scan_batch(ctx, _addr(samples, 4 * num_samples, "samples"), num_samples,
+                             _addr(desc, 24 * num_series, "desc"), num_series, ctypes.byref(params),
+                             _addr(out, 48 * num_series, "out"), _addr(all_U, None, "all_U"), all_U_len,
+                             _stream(stream))
+    _check(rc, "ks_scan_batch")
+
+
+# ---------------------------------------------------------------- convenience
+
+
+def make_desc(offsets, Ks, Ns, aux_offsets=None) -> np.ndarray:
+    d = np.zeros(len(Ks), DESC_DTYPE)
+    d["offset"] = offsets
+    d["K"] = Ks
+    d["N"] = Ns
+    if aux_offsets is None:
+        aux = np.zeros(len(Ks), np.uint64)
+        if len(Ks):
+            aux[1:] = np.cumsum(np.asarray(Ks, np.uint64))[:-1]
+        d["aux_offset"] = aux
+    else:
+        d["aux_offset"] = aux_offsets
+    return d
+
+
+def to_device(a: np.ndarray, device="cuda"):
+    """Copy a numpy array's bytes into a device uint8 tensor (uint32 arrays become int32 tensors)."""
+    import torch
+
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        return torch.from_numpy(a.view(np.int32)).to(device)
+    return torch.from_numpy(a.view(np.uint8).reshape(-1)).to(device)
+
+
+def empty_results(num_series: int, device="cuda"):
+    import torch
+
+    return torch.empty(num_series * RESULT_DTYPE.itemsize, dtype=torch.uint8, device=device)
+
+
+def results_to_numpy(out) -> np.ndarray:
+    return out.cpu().numpy().view(RESULT_DTYPE)
+
+
+class Context:
+    """Owns one ks_ctx (ks_ctx_create / ks_ctx_destroy)."""
+
+    def __init__(self, device: int = 0):
+        self.handle = ks_ctx_create(device)
+
+    def close(self):
+        if self.handle is not None:
+            ks_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

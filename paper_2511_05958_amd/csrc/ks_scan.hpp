@@ -1,0 +1,411 @@
+// Exact K-S change-point scan of one series per workgroup (gfx950).
+//
+// Per series (one workgroup of NT threads, NT/64 waves):
+//   1. stream the K x N uint32 samples once: per row sum r and sum r^2
+//      (96-bit), and the running minimum (eq. 2 needs the minimum over the
+//      whole 2-D array);
+//   2. Q_i = sum r^2 - 2 m sum r + N m^2 = sum_j (r_ij - m)^2, exact;
+//   3. LDS LSD radix sort of the K (Q_i, i) pairs, RB-bit digits, only as
+//      many passes as Q's bit length needs; mark the ends of equal-key groups;
+//   4. lattice walk: for each candidate c, U_c = max over group ends p of
+//      |K i_c(p) - c (p + 1)| with i_c(p) = #{q <= p : row(q) < c}, by
+//      ballot / mbcnt prefix counts over 64 sorted positions at a time
+//      (this is max |i m - j n| with j = p + 1 - i, the D numerator);
+//   5. exact argmax of U_c^2 / (c (K - c)), eq. 1 significance, FP64
+//      Kolmogorov p-value of the winner only.
+#pragma once
+
+#include "ks.h"
+#include "ks_wave.hpp"
+
+namespace ks {
+
+typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------- LDS layout
+
+template <int KMAX, int NT, int RB>
+struct ScanShape {
+  static constexpr int W = NT / kWave;              // waves per workgroup
+  static constexpr int T = (KMAX + NT - 1) / NT;    // sort tiles
+  static constexpr int D = 1 << RB;                 // radix buckets
+  static constexpr int H = D * T * W;               // (digit, tile, wave) counters
+  static constexpr int CH = (KMAX + kWave - 1) / kWave;  // 64-position chunks
+};
+
+template <int KMAX, int NT, int RB>
+struct ScanSmem {
+  using S = ScanShape<KMAX, NT, RB>;
+  union {
+    struct {  // phase 1: per-row moments
+      uint64_t s1[KMAX];
+      uint64_t s2lo[KMAX];
+      uint32_t s2hi[KMAX];
+    } mom;
+    struct {  // sort pong buffer (moments are dead once the keys exist)
+      uint32_t key[3][KMAX];
+      uint16_t idx[KMAX];
+    } pong;
+  } u;
+  uint32_t key[3][KMAX];  // sort ping buffer: Q as three 32-bit words
+  uint16_t idx[KMAX];
+  uint64_t tie[S::CH];    // bit p%64 of tie[p/64]: sorted position p ends a group of equal Q
+  uint16_t hist[S::H];
+  uint32_t red[S::W * 4];
+  uint32_t bestU[S::W], bestC[S::W];
+};
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ void acc_sample(uint32_t x, uint32_t& mn, uint64_t& s1, uint64_t& s2, uint32_t& s2h) {
+  mn = min(mn, x);
+  s1 += x;
+  const uint64_t p = (uint64_t)x * x;
+  s2 += p;
+  s2h += (uint32_t)(s2 < p);
+}
+
+__device__ __forceinline__ uint32_t key_digit(uint32_t k0, uint32_t k1, uint32_t k2, int shift, uint32_t mask) {
+  const int w = shift >> 5, o = shift & 31;
+  const uint32_t a = w == 0 ? k0 : (w == 1 ? k1 : k2);
+  const uint32_t b = w == 0 ? k1 : (w == 1 ? k2 : 0u);
+  return (uint32_t)((((uint64_t)b << 32) | a) >> o) & mask;
+}
+
+// Does candidate a beat candidate b? lambda^2 = U^2 / (c (K - c) K); compared
+// exactly by cross-multiplying (U^2 <= 2^40, c (K - c) <= 2^20).
+__device__ __forceinline__ bool more_significant(uint32_t Ua, uint32_t a, uint32_t Ub, uint32_t b, uint32_t K) {
+  const uint64_t lhs = (uint64_t)Ua * Ua * ((uint64_t)b * (K - b));
+  const uint64_t rhs = (uint64_t)Ub * Ub * ((uint64_t)a * (K - a));
+  return lhs > rhs || (lhs == rhs && a < b);
+}
+
+// Asymptotic Kolmogorov tail from lambda^2: the alternating exp(-2 k^2 l^2)
+// series for lambda >= 1, the Jacobi-theta form below; each stops once a term
+// is under 1e-20 of the sum; 0 once 2 lambda^2 > 700.
+__device__ double kolmogorov_q(double lambda2) {
+  if (!(lambda2 > 0.0)) return 1.0;
+  if (2.0 * lambda2 > 700.0) return 0.0;
+  double sum = 0.0;
+  if (lambda2 >= 1.0) {
+    for (int k = 1; k <= 200; ++k) {
+      const double term = exp(-2.0 * lambda2 * (double)(k * k));
+      sum += (k & 1) ? term : -term;
+      if (term < 1e-20 * fabs(sum)) break;
+    }
+    return 2.0 * sum;
+  }
+  const double pi = 3.141592653589793;
+  const double lam = sqrt(lambda2);
+  for (int k = 1; k <= 200; ++k) {
+    const double o = (double)(2 * k - 1);
+    const double term = exp(-(o * o * pi * pi) / (8.0 * lambda2));
+    sum += term;
+    if (term < 1e-20 * sum) break;
+  }
+  return 1.0 - sqrt(2.0 * pi) / lam * sum;
+}
+
+__device__ __forceinline__ void write_result(ks_result* o, uint32_t cp, uint32_t n, uint32_t m, uint32_t U, double D,
+                                             double lam, double p, uint32_t flags) {
+  o->cp = cp;
+  o->n = n;
+  o->m = m;
+  o->U = U;
+  o->D = D;
+  o->lambda = lam;
+  o->p = p;
+  o->flags = flags;
+  o->pad = 0;
+}
+
+// ---------------------------------------------------------------- phases
+
+// Phase 1: per-row moments into LDS; returns the series minimum (block-uniform).
+template <int KMAX, int NT, int RB>
+__device__ uint32_t stream_moments(ScanSmem<KMAX, NT, RB>& sm, const uint32_t* __restrict__ base, uint32_t K,
+                                   uint32_t N, bool vec4) {
+  using S = ScanShape<KMAX, NT, RB>;
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  uint32_t mn = 0xffffffffu;
+  for (uint32_t i = w; i < K; i += S::W) {
+    const uint32_t* row = base + (uint64_t)i * N;
+    uint64_t s1 = 0, s2 = 0;
+    uint32_t s2h = 0;
+    if (vec4) {
+      const u32x4* r4 = reinterpret_cast<const u32x4*>(row);
+      const uint32_t n4 = N >> 2;
+      uint32_t q = lane;
+      for (; q + 3 * kWave < n4; q += 4 * kWave) {
+        const u32x4 a = __builtin_nontemporal_load(r4 + q);
+        const u32x4 b = __builtin_nontemporal_load(r4 + q + kWave);
+        const u32x4 c = __builtin_nontemporal_load(r4 + q + 2 * kWave);
+        const u32x4 d = __builtin_nontemporal_load(r4 + q + 3 * kWave);
+        acc_sample(a.x, mn, s1, s2, s2h); acc_sample(a.y, mn, s1, s2, s2h);
+        acc_sample(a.z, mn, s1, s2, s2h); acc_sample(a.w, mn, s1, s2, s2h);
+        acc_sample(b.x, mn, s1, s2, s2h); acc_sample(b.y, mn, s1, s2, s2h);
+        acc_sample(b.z, mn, s1, s2, s2h); acc_sample(b.w, mn, s1, s2, s2h);
+        acc_sample(c.x, mn, s1, s2, s2h); acc_sample(c.y, mn, s1, s2, s2h);
+        acc_sample(c.z, mn, s1, s2, s2h); acc_sample(c.w, mn, s1, s2, s2h);
+        acc_sample(d.x, mn, s1, s2, s2h); acc_sample(d.y, mn, s1, s2, s2h);
+        acc_sample(d.z, mn, s1, s2, s2h); acc_sample(d.w, mn, s1, s2, s2h);
+      }
+      for (; q < n4; q += kWave) {
+        const u32x4 a = __builtin_nontemporal_load(r4 + q);
+        acc_sample(a.x, mn, s1, s2, s2h); acc_sample(a.y, mn, s1, s2, s2h);
+        acc_sample(a.z, mn, s1, s2, s2h); acc_sample(a.w, mn, s1, s2, s2h);
+      }
+    } else {
+      uint32_t q = lane;
+      for (; q + 3 * kWave < N; q += 4 * kWave) {
+        const uint32_t a = __builtin_nontemporal_load(row + q);
+        const uint32_t b = __builtin_nontemporal_load(row + q + kWave);
+        const uint32_t c = __builtin_nontemporal_load(row + q + 2 * kWave);
+        const uint32_t d = __builtin_nontemporal_load(row + q + 3 * kWave);
+        acc_sample(a, mn, s1, s2, s2h); acc_sample(b, mn, s1, s2, s2h);
+        acc_sample(c, mn, s1, s2, s2h); acc_sample(d, mn, s1, s2, s2h);
+      }
+      for (; q < N; q += kWave) acc_sample(__builtin_nontemporal_load(row + q), mn, s1, s2, s2h);
+    }
+    s1 = wave_sum_u64(s1);
+    wave_sum_u96(s2, s2h);
+    if (lane == 0) {
+      sm.u.mom.s1[i] = s1;
+      sm.u.mom.s2lo[i] = s2;
+      sm.u.mom.s2hi[i] = s2h;
+    }
+  }
+  mn = wave_min_u32(mn);
+  if (lane == 0) sm.red[w] = mn;
+  __syncthreads();
+  uint32_t g = sm.red[0];
+#pragma unroll
+  for (int v = 1; v < S::W; ++v) g = min(g, sm.red[v]);
+  __syncthreads();
+  return g;
+}
+
+// Phase 2: Q_i keys (ping buffer) and their OR (for the number of radix passes).
+template <int KMAX, int NT, int RB>
+__device__ int make_keys(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N, uint32_t gmin) {
+  using S = ScanShape<KMAX, NT, RB>;
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  uint32_t o0 = 0, o1 = 0, o2 = 0;
+  const u128 nm2 = (u128)((uint64_t)gmin * gmin) * N;
+  const uint64_t twom = 2ull * gmin;
+  for (uint32_t i = threadIdx.x; i < K; i += NT) {
+    const u128 s2 = ((u128)sm.u.mom.s2hi[i] << 64) | sm.u.mom.s2lo[i];
+    const u128 q = s2 + nm2 - (u128)sm.u.mom.s1[i] * twom;
+    const uint32_t k0 = (uint32_t)q, k1 = (uint32_t)(q >> 32), k2 = (uint32_t)(q >> 64);
+    sm.key[0][i] = k0;
+    sm.key[1][i] = k1;
+    sm.key[2][i] = k2;
+    sm.idx[i] = (uint16_t)i;
+    o0 |= k0;
+    o1 |= k1;
+    o2 |= k2;
+  }
+  o0 = wave_or_u32(o0);
+  o1 = wave_or_u32(o1);
+  o2 = wave_or_u32(o2);
+  if (lane == 0) {
+    sm.red[w * 4 + 0] = o0;
+    sm.red[w * 4 + 1] = o1;
+    sm.red[w * 4 + 2] = o2;
+  }
+  __syncthreads();
+  uint32_t a = 0, b = 0, c = 0;
+#pragma unroll
+  for (int v = 0; v < S::W; ++v) {
+    a |= sm.red[v * 4 + 0];
+    b |= sm.red[v * 4 + 1];
+    c |= sm.red[v * 4 + 2];
+  }
+  __syncthreads();
+  if (c) return 96 - __clz(c);
+  if (b) return 64 - __clz(b);
+  if (a) return 32 - __clz(a);
+  return 0;
+}
+
+// Phase 3: stable LSD radix sort of (key, idx); returns true if the sorted
+// data ended in the pong buffer.
+template <int KMAX, int NT, int RB>
+__device__ bool sort_keys(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, int bits) {
+  using S = ScanShape<KMAX, NT, RB>;
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave, tid = threadIdx.x;
+  const int passes = (bits + RB - 1) / RB;
+  constexpr int C = (S::H + NT - 1) / NT;
+  for (int p = 0; p < passes; ++p) {
+    const bool from_ping = (p & 1) == 0;
+    uint32_t(*ka)[KMAX] = from_ping ? sm.key : sm.u.pong.key;
+    uint16_t* ia = from_ping ? sm.idx : sm.u.pong.idx;
+    uint32_t(*kb)[KMAX] = from_ping ? sm.u.pong.key : sm.key;
+    uint16_t* ib = from_ping ? sm.u.pong.idx : sm.idx;
+    const int shift = p * RB;
+    for (int h = tid; h < S::H; h += NT) sm.hist[h] = 0;
+    __syncthreads();
+    uint32_t dg[S::T], rk[S::T];
+#pragma unroll
+    for (int t = 0; t < S::T; ++t) {
+      const uint32_t item = t * NT + tid;
+      const bool valid = item < K;
+      const uint32_t d = valid ? key_digit(ka[0][item], ka[1][item], ka[2][item], shift, S::D - 1) : 0u;
+      uint64_t peers = ballot(valid);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      dg[t] = d;
+      rk[t] = mbcnt(peers);
+      if (valid && rk[t] == 0) sm.hist[(d * S::T + t) * S::W + w] = (uint16_t)__popcll(peers);
+    }
+    __syncthreads();
+    // exclusive scan of hist in (digit, tile, wave) order
+    uint32_t local = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int h = tid * C + c;
+      if (h < S::H) local += sm.hist[h];
+    }
+    const uint32_t incl = wave_incl_scan(local);
+    if (lane == kWave - 1) sm.red[w] = incl;
+    __syncthreads();
+    uint32_t run = incl - local;
+    for (uint32_t v = 0; v < w; ++v) run += sm.red[v];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int h = tid * C + c;
+      if (h < S::H) {
+        const uint32_t x = sm.hist[h];
+        sm.hist[h] = (uint16_t)run;
+        run += x;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < S::T; ++t) {
+      const uint32_t item = t * NT + tid;
+      if (item < K) {
+        const uint32_t dst = sm.hist[(dg[t] * S::T + t) * S::W + w] + rk[t];
+        kb[0][dst] = ka[0][item];
+        kb[1][dst] = ka[1][item];
+        kb[2][dst] = ka[2][item];
+        ib[dst] = ia[item];
+      }
+    }
+    __syncthreads();
+  }
+  return (passes & 1) != 0;
+}
+
+// Phases 4-5 for one series already holding moments in LDS.
+template <int KMAX, int NT, int RB>
+__device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N, uint32_t gmin,
+                              const ks_params& prm, ks_result* __restrict__ out, uint32_t* __restrict__ allU) {
+  using S = ScanShape<KMAX, NT, RB>;
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  const int bits = make_keys(sm, K, N, gmin);
+  const bool in_pong = sort_keys(sm, K, bits);
+  uint32_t(*ks)[KMAX] = in_pong ? sm.u.pong.key : sm.key;
+  const uint16_t* is = in_pong ? sm.u.pong.idx : sm.idx;
+
+  // ends of equal-key groups
+  for (uint32_t p0 = w * kWave; p0 < K; p0 += NT) {
+    const uint32_t p = p0 + lane;
+    bool end = false;
+    if (p + 1 < K)
+      end = ks[0][p] != ks[0][p + 1] || ks[1][p] != ks[1][p + 1] || ks[2][p] != ks[2][p + 1];
+    else if (p + 1 == K)
+      end = true;
+    const uint64_t m = ballot(end);
+    if (lane == 0) sm.tie[p0 / kWave] = m;
+  }
+  __syncthreads();
+
+  // lattice walk over the candidates c = 1 + w, 1 + w + W, ...
+  const uint32_t nch = (K + kWave - 1) / kWave;
+  uint32_t bU = 0, bC = 0;
+  for (uint32_t c = 1 + w; c < K; c += S::W) {
+    uint32_t carry = 0, mx = 0;
+    for (uint32_t k = 0; k < nch; ++k) {
+      const uint32_t p = k * kWave + lane;
+      const uint32_t row = p < K ? (uint32_t)is[p] : 0xffffffffu;
+      const bool lt = row < c;
+      const uint64_t msk = ballot(lt);
+      const uint32_t incl = carry + mbcnt(msk) + (lt ? 1u : 0u);
+      const int32_t f = (int32_t)(K * incl) - (int32_t)(c * (p + 1));
+      const uint32_t af = (uint32_t)(f < 0 ? -f : f);
+      if ((sm.tie[k] >> lane) & 1ull) mx = max(mx, af);
+      carry += (uint32_t)__popcll(msk);
+    }
+    const uint32_t Uc = wave_max_u32(mx);
+    if (allU && lane == 0) allU[c] = Uc;
+    if (bC == 0 || more_significant(Uc, c, bU, bC, K)) {
+      bU = Uc;
+      bC = c;
+    }
+  }
+  if (lane == 0) {
+    sm.bestU[w] = bU;
+    sm.bestC[w] = bC;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t U = sm.bestU[0], c = sm.bestC[0];
+    for (int v = 1; v < S::W; ++v)
+      if (sm.bestC[v] != 0 && (c == 0 || more_significant(sm.bestU[v], sm.bestC[v], U, c, K))) {
+        U = sm.bestU[v];
+        c = sm.bestC[v];
+      }
+    if (allU) allU[0] = 0;
+    const uint32_t n = c, m = K - c;
+    const double U2 = (double)((uint64_t)U * U);
+    const double nmK = (double)((uint64_t)n * m * K);
+    const double lambda2 = U2 / nmK;
+    const double p = U == 0 ? 1.0 : kolmogorov_q(lambda2);
+    const uint32_t flags = (U2 > prm.c_alpha * nmK) ? KS_SIGNIFICANT : 0u;
+    write_result(out, c, n, m, U, (double)U / (double)((uint64_t)n * m), sqrt(lambda2), p, flags);
+  }
+  __syncthreads();
+}
+
+// Shape / range validation of one descriptor (uniform across the workgroup).
+__device__ __forceinline__ uint32_t check_desc(const ks_desc& d, uint64_t num_samples, uint32_t max_K) {
+  if (d.K < 2 || d.K > max_K || d.N < 1 || d.N > KS_MAX_N) return KS_BAD_SHAPE;
+  if (d.offset > num_samples || (uint64_t)d.K * d.N > num_samples - d.offset) return KS_OUT_OF_RANGE;
+  return 0;
+}
+
+template <int KMAX, int NT, int RB>
+__device__ void scan_one(ScanSmem<KMAX, NT, RB>& sm, const uint32_t* __restrict__ samples, uint64_t num_samples,
+                         const ks_desc& d, const ks_params& prm, uint32_t max_K, ks_result* __restrict__ out,
+                         uint32_t* __restrict__ allU, uint64_t allU_len) {
+  const uint32_t bad = check_desc(d, num_samples, max_K);
+  if (bad) {
+    if (threadIdx.x == 0) write_result(out, 0, 0, 0, 0, 0.0, 0.0, 1.0, bad);
+    return;
+  }
+  const uint32_t* base = samples + d.offset;
+  const bool vec4 = ((d.offset | d.N) & 3u) == 0 && ((uintptr_t)samples & 15u) == 0;
+  const uint32_t gmin = stream_moments(sm, base, d.K, d.N, vec4);
+  const bool fits = allU && d.aux_offset <= allU_len && d.K <= allU_len - d.aux_offset;
+  finish_series(sm, d.K, d.N, gmin, prm, out, fits ? allU + d.aux_offset : nullptr);
+}
+
+// One workgroup per series.
+template <int KMAX, int NT, int RB>
+__global__ __launch_bounds__(NT) void scan_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
+                                                  const ks_desc* __restrict__ desc, uint32_t num_series,
+                                                  ks_params prm, uint32_t max_K, ks_result* __restrict__ out,
+                                                  uint32_t* __restrict__ allU, uint64_t allU_len) {
+  __shared__ ScanSmem<KMAX, NT, RB> sm;
+  const uint32_t s = blockIdx.x;
+  if (s >= num_series) return;
+  const ks_desc d = desc[s];
+  scan_one(sm, samples, num_samples, d, prm, max_K, out + s, allU, allU_len);
+}
+
+}  // namespace ks
