@@ -11,6 +11,8 @@ Workloads (seeded synthetic sweeps, see paper_2511_05958_amd.synth):
   c2  4096 series, K=256, N=1024        (default; 4 GiB of samples)
   c3  16384 uneven series, K~logU[32,512], N~logU[64,4096]
   c5  8192 series, K=1024, N=2048       (64 GiB of samples)
+  copy  a plain device-to-device copy of 1 GiB (the reference kernel that
+        calibrates the FETCH_SIZE / WRITE_SIZE counters; prints bytes moved)
 """
 
 from __future__ import annotations
@@ -31,25 +33,64 @@ WORKLOADS = {
 }
 
 
-def cpu_baseline(batch, sample_series: int, threads: int) -> dict:
-    """The CPU oracle, as it stands, on a bounded sample of the same workload."""
+def cpu_baseline(batch, samples_dev, threads: int, target_s: float = 10.0, max_bytes: int = 2 << 30) -> dict:
+    """The CPU oracle, as it stands, on a bounded sample of the same workload.
+
+    The first series of the batch (already in HBM) are copied to the host; a
+    64-series probe estimates the oracle's rate, then enough further series
+    for about target_s seconds of oracle work (at most max_bytes of samples,
+    at most the whole batch) are timed."""
     import numpy as np
 
     import oracle as O
-    from paper_2511_05958_amd import synth as S
 
-    sub = batch.subset(np.arange(min(sample_series, batch.num_series)))
-    x = S.fill_host(sub, threads=threads)
+    sp = batch.specs
+    ends = sp["offset"].astype(np.int64) + sp["K"].astype(np.int64) * sp["N"].astype(np.int64)
+    fit = int(np.searchsorted(ends, max_bytes // 4, side="right"))
+    limit = max(1, min(batch.num_series, fit))
+
+    def host_prefix(count):
+        return samples_dev[: int(ends[count - 1])].cpu().numpy().view(np.uint32)
+
+    probe = min(limit, 64)
+    x = host_prefix(probe)
     t0 = time.perf_counter()
-    O.scan_batch(x, sub.specs["offset"], sub.specs["K"], sub.specs["N"], threads=threads)
+    O.scan_batch(x, sp["offset"][:probe], sp["K"][:probe], sp["N"][:probe], threads=threads)
+    rate = probe / max(time.perf_counter() - t0, 1e-9)
+    count = int(min(limit, max(probe, rate * target_s)))
+    x = host_prefix(count)
+    t0 = time.perf_counter()
+    O.scan_batch(x, sp["offset"][:count], sp["K"][:count], sp["N"][:count], threads=threads)
     dt = time.perf_counter() - t0
     return {
-        "value": sub.num_series / dt,
+        "value": count / dt,
         "unit": "series/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"first {sub.num_series} series of the same batch, {threads} threads, {dt:.2f} s",
+        "sample": f"first {count} of {batch.num_series} series of the same batch "
+                  f"({4 * int(ends[count - 1]) / 2**30:.2f} GiB), {threads} threads, {dt:.2f} s",
     }
+
+
+def copy_calibration(args) -> int:
+    import torch
+
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    print(json.dumps({"workload": "copy", "read_bytes": nbytes, "write_bytes": nbytes, "ms": ms,
+                      "GBps_read_plus_write": 2 * nbytes / ms / 1e6}), flush=True)
+    return 0
 
 
 def main() -> int:
@@ -57,9 +98,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=0, help="series in the CPU sample (0 = auto)")
+    ap.add_argument("--launch", default="autotune",
+                    choices=["autotune", "default", "grid", "ordered", "persistent", "persistent-direct"],
+                    help="launch plan: autotune (time the candidates first, untimed), the library default, "
+                         "one workgroup per series, largest-first ordered grid, persistent queue (hipGraph), "
+                         "persistent queue with direct launches")
+    ap.add_argument("--chunk", type=int, default=1 << 20, help="split size of the persistent plan (bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -72,6 +118,8 @@ def main() -> int:
     import paper_2511_05958_amd as P
     from paper_2511_05958_amd import synth as S
 
+    if args.workload == "copy":
+        return copy_calibration(args)
     recipe, count, label = WORKLOADS[args.workload]
     batch = S.make_batch(recipe, num_series=count)
     n = batch.num_series
@@ -84,6 +132,18 @@ def main() -> int:
     prm.max_K = int(batch.specs["K"].max())
     ctx = P.Context(0)
     stream = torch.cuda.current_stream(dev)
+    chosen = None
+    if args.launch == "autotune":
+        best, _ = P.ks_autotune(ctx.handle, samples, desc, n, prm, out, stream=stream)
+        chosen = {"mode": best.mode, "chunk_bytes": best.chunk_bytes, "graph": best.graph}
+    elif args.launch != "default":
+        cfg = {"grid": (P.KS_LAUNCH_GRID, args.chunk, 0), "ordered": (P.KS_LAUNCH_ORDERED, args.chunk, 1),
+               "persistent": (P.KS_LAUNCH_PERSISTENT, args.chunk, 1),
+               "persistent-direct": (P.KS_LAUNCH_PERSISTENT, args.chunk, 0)}[args.launch]
+        P.ks_launch_set(ctx.handle, prm.max_K, n, *cfg)
+    if chosen is None:
+        c = P.ks_launch_get(ctx.handle, prm.max_K, n)
+        chosen = {"mode": c.mode, "chunk_bytes": c.chunk_bytes, "graph": c.graph}
 
     def step():
         P.ks_scan_batch(ctx.handle, samples, desc, n, prm, out, stream=stream)
@@ -127,6 +187,7 @@ def main() -> int:
             "sample_bytes": batch.sample_bytes,
             "max_K": prm.max_K,
             "alpha": prm.alpha,
+            "launch": chosen,
             "significant": int(np.count_nonzero(res["flags"] & P.KS_SIGNIFICANT)),
             "flagged_bad": bad,
         },
@@ -137,14 +198,13 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "ks::scan_kernel",
+            "kernel": "ks::scan_persistent" if chosen["mode"] == P.KS_LAUNCH_PERSISTENT else "ks::scan_kernel",
             "kernel_ms": avg_kern_s * 1e3,
         },
     }
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        sample = args.cpu_sample or {1: 1, 2: 512, 3: 512, 5: 48}[recipe]
-        line["cpu_baseline"] = cpu_baseline(batch, sample, threads)
+        threads = min(16, len(os.sched_getaffinity(0)))
+        line["cpu_baseline"] = cpu_baseline(batch, samples, threads)
     ctx.close()
     print(json.dumps(line), flush=True)
     return 0

@@ -33,7 +33,9 @@
  *   - Streams: `stream` is a hipStream_t of the context's device (NULL = the
  *     null stream). Calls are asynchronous and stream-ordered; results are
  *     valid once the stream's work up to the call has completed.
- *   - Contexts are not thread-safe: use one ks_ctx per host thread.
+ *   - Contexts are not thread-safe: use one ks_ctx per host thread. The calls
+ *     of one context share its device workspace, so they must be ordered on
+ *     one stream (or the caller waits between streams).
  */
 #ifndef KS_H
 #define KS_H
@@ -103,7 +105,7 @@ typedef struct ks_result {
  *   w        refine half-window (ks_refine), 1..64, default 8
  *   tau      confidence threshold of ks_refine in [0, 1]; below it the full
  *            scan runs (default 0.5)
- *   opts     reserved, must be 0 */
+ *   opts     KS_OPT_* launch overrides (0 = the tuned or default plan) */
 typedef struct ks_params {
   double alpha;
   double c_alpha;
@@ -112,6 +114,12 @@ typedef struct ks_params {
   float tau;
   uint32_t opts;
 } ks_params;
+
+/* ks_params.opts: launch overrides, for measurement and tuning. */
+#define KS_OPT_GRID 1u        /* force KS_LAUNCH_GRID */
+#define KS_OPT_PERSISTENT 2u  /* force KS_LAUNCH_PERSISTENT */
+#define KS_OPT_NO_GRAPH 4u    /* launch the plan's kernels directly instead of a hipGraph */
+#define KS_OPT_MASK 7u
 
 typedef struct ks_ctx ks_ctx;
 
@@ -149,10 +157,58 @@ int ks_reserve(ks_ctx *ctx, uint32_t max_series, uint64_t max_total_steps);
  * num_series == 0 is a no-op. Per-series shape or range errors are reported
  * in out[s].flags (cp = 0), not as a status. KS_E_INVALID on a NULL pointer
  * or a bad alpha / c_alpha / w / tau / opts, KS_E_RANGE on max_K outside
- * [2, KS_MAX_K] (0 allowed). */
+ * [2, KS_MAX_K] (0 allowed), KS_E_NOMEM if the workspace cannot grow.
+ *
+ * Launch plan (ks_launch_set / ks_autotune; default KS_LAUNCH_ORDERED): an
+ * on-device planning kernel orders the series largest first, then either one
+ * workgroup per series in that order, or a persistent kernel drains the
+ * ordered items (large series split into row ranges whose moments meet in
+ * the workspace) followed by a finish kernel. Planned launches are replayed
+ * from a hipGraph cached per (mode, max_K class, grid) with updated
+ * arguments. The workspace grows on demand (that growth synchronizes the
+ * device); ks_reserve avoids it. */
 int ks_scan_batch(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, const ks_desc *desc,
                   uint32_t num_series, const ks_params *params, ks_result *out, uint32_t *all_U,
                   uint64_t all_U_len, void *stream);
+
+/* ks_launch.mode */
+#define KS_LAUNCH_GRID 0u        /* one workgroup per series, descriptor order, no plan */
+#define KS_LAUNCH_PERSISTENT 1u  /* plan + persistent queue over (split) items + finish kernel */
+#define KS_LAUNCH_ORDERED 2u     /* plan + one workgroup per series, largest series first */
+
+/* Launch plan for one batch shape (max_K class, num_series).
+ *   mode         KS_LAUNCH_*
+ *   chunk_bytes  split size of KS_LAUNCH_PERSISTENT, 4 KiB .. 1 GiB: series
+ *                with more sample bytes are cut into row ranges of about
+ *                this size (at most 64 per series)
+ *   graph        1: replay a planned launch from a cached hipGraph;
+ *                0: launch its kernels directly */
+typedef struct ks_launch {
+  uint32_t mode;
+  uint32_t chunk_bytes;
+  uint32_t graph;
+  uint32_t pad;
+} ks_launch;
+
+/* Record (ks_launch_set) or read (ks_launch_get) the plan ks_scan_batch uses
+ * for batches with this max_K class and num_series; without a record the
+ * default is {KS_LAUNCH_ORDERED, 1 MiB, 1}. KS_E_INVALID / KS_E_RANGE on bad
+ * values. */
+int ks_launch_set(ks_ctx *ctx, uint32_t max_K, uint32_t num_series, const ks_launch *cfg);
+int ks_launch_get(ks_ctx *ctx, uint32_t max_K, uint32_t num_series, ks_launch *cfg);
+
+/* Autotuner: time every candidate plan (grid; ordered grid from a hipGraph
+ * and direct; persistent with chunk_bytes 1, 4, 16 MiB, from a hipGraph and
+ * direct) on this
+ * very batch with HIP events on `stream` (one warm-up, best of three), record
+ * the fastest with ks_launch_set, and return it in *best (nullable) and its
+ * time in *best_ms (nullable). Blocks until done; writes `out`. When the
+ * environment variable KS_TUNE_CACHE names a file, the choice is appended to
+ * it, and ks_ctx_create loads the records written for the same device
+ * (architecture and CU count). Arguments as ks_scan_batch. */
+int ks_autotune(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, const ks_desc *desc,
+                uint32_t num_series, const ks_params *params, ks_result *out, void *stream, ks_launch *best,
+                float *best_ms);
 
 #ifdef __cplusplus
 }

@@ -27,6 +27,10 @@ KS_E_HIP = -4
 KS_E_MODEL = -5
 KS_E_NOMEM = -6
 
+KS_OPT_GRID = 1
+KS_OPT_PERSISTENT = 2
+KS_OPT_NO_GRAPH = 4
+
 KS_SIGNIFICANT = 1
 KS_REFINED = 2
 KS_FALLBACK = 4
@@ -49,6 +53,16 @@ class ks_params(ctypes.Structure):
 assert ctypes.sizeof(ks_params) == 32
 
 
+KS_LAUNCH_GRID = 0
+KS_LAUNCH_PERSISTENT = 1
+KS_LAUNCH_ORDERED = 2
+
+
+class ks_launch(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32), ("graph", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
 class KsError(RuntimeError):
     def __init__(self, code: int, what: str):
         super().__init__(f"{what}: {ks_status_string(code)} ({code})")
@@ -69,6 +83,9 @@ _SIGNATURES = {
     "ks_ctx_destroy": ([_vp], ctypes.c_int),
     "ks_reserve": ([_vp, _u32, _u64], ctypes.c_int),
     "ks_scan_batch": ([_vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp, _u64, _vp], ctypes.c_int),
+    "ks_launch_set": ([_vp, _u32, _u32, _vp], ctypes.c_int),
+    "ks_launch_get": ([_vp, _u32, _u32, _vp], ctypes.c_int),
+    "ks_autotune": ([_vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
 }
 
 
@@ -165,6 +182,33 @@ def ks_scan_batch(ctx, samples, desc, num_series: int, params: ks_params, out, a
                              _addr(out, 48 * num_series, "out"), _addr(all_U, None, "all_U"), all_U_len,
                              _stream(stream))
     _check(rc, "ks_scan_batch")
+
+
+def ks_launch_set(ctx, max_K: int, num_series: int, mode: int = KS_LAUNCH_ORDERED, chunk_bytes: int = 1 << 20,
+                  graph: int = 1) -> None:
+    cfg = ks_launch(mode, chunk_bytes, graph, 0)
+    _check(lib().ks_launch_set(ctx, max_K, num_series, ctypes.byref(cfg)), "ks_launch_set")
+
+
+def ks_launch_get(ctx, max_K: int, num_series: int) -> ks_launch:
+    cfg = ks_launch()
+    _check(lib().ks_launch_get(ctx, max_K, num_series, ctypes.byref(cfg)), "ks_launch_get")
+    return cfg
+
+
+def ks_autotune(ctx, samples, desc, num_series: int, params: ks_params, out, stream=None,
+                num_samples: int | None = None) -> tuple[ks_launch, float]:
+    """Time the candidate launch plans on this batch; record and return the fastest (and its ms)."""
+    if num_samples is None:
+        num_samples = samples.numel() * samples.element_size() // 4
+    best = ks_launch()
+    ms = ctypes.c_float(0.0)
+    rc = lib().ks_autotune(ctx, _addr(samples, 4 * num_samples, "samples"), num_samples,
+                           _addr(desc, 24 * num_series, "desc"), num_series, ctypes.byref(params),
+                           _addr(out, 48 * num_series, "out"), _stream(stream), ctypes.byref(best),
+                           ctypes.byref(ms))
+    _check(rc, "ks_autotune")
+    return best, float(ms.value)
 
 
 # ---------------------------------------------------------------- convenience

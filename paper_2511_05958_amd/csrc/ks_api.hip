@@ -1,20 +1,64 @@
-// C ABI of the K-S change-point library: contexts, validation, launches.
+// C ABI of the K-S change-point library: contexts, workspace, validation,
+// launch plans (direct grid or planned persistent launch captured in a
+// hipGraph) and the tuning table.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <string>
 #include <new>
+#include <tuple>
 
 #include "ks.h"
-#include "ks_scan.hpp"
+#include "ks_persist.hpp"
+
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kRB = 4;
+constexpr int kNumKClasses = 6;
+constexpr uint32_t kKClass[kNumKClasses] = {64, 128, 256, 512, 1024, 2048};
+
+int k_class(uint32_t max_K) {
+  for (int i = 0; i < kNumKClasses; ++i)
+    if (max_K <= kKClass[i]) return i;
+  return kNumKClasses - 1;
+}
+
+// Launch configuration chosen per (K class) and batch size by the tuner.
+struct LaunchCfg {
+  int mode = KS_LAUNCH_ORDERED;  // KS_LAUNCH_GRID / _PERSISTENT / _ORDERED
+  uint32_t chunk_bytes = 1u << 20;
+  int graph = 1;                 // planned launches replayed from a hipGraph
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node[3] = {nullptr, nullptr, nullptr};
+  int nodes = 0;
+};
+
+}  // namespace
 
 struct ks_ctx {
   int device = 0;
   int num_cus = 0;
-  size_t lds_per_block = 0;
-  uint32_t reserved_series = 0;
-  uint64_t reserved_steps = 0;
+  std::string arch;
+  int occupancy[kNumKClasses] = {0};  // resident workgroups per CU of scan_persistent
+  // workspace
+  uint32_t* hdr = nullptr;
+  ks::Item* items = nullptr;
+  uint64_t* mom_base = nullptr;
+  uint32_t* done = nullptr;
+  uint32_t* smin = nullptr;
+  ks::RowMom* mom = nullptr;
+  uint64_t cap_series = 0, cap_rows = 0;
+  std::map<std::tuple<int, int, uint32_t>, GraphEntry> graphs;  // (mode, K class, grid)
+  std::map<std::tuple<int, uint32_t>, LaunchCfg> tuned;     // (K class, num_series)
 };
 
 namespace {
@@ -49,21 +93,248 @@ int check_params(const ks_params* p) {
   if (!(p->c_alpha > 0.0) || !std::isfinite(p->c_alpha)) return KS_E_INVALID;
   if (p->w < 1 || p->w > 64) return KS_E_INVALID;
   if (!(p->tau >= 0.0f && p->tau <= 1.0f)) return KS_E_INVALID;
-  if (p->opts != 0) return KS_E_INVALID;
+  if (p->opts & ~(uint32_t)KS_OPT_MASK) return KS_E_INVALID;
   if (p->max_K != 0 && (p->max_K < 2 || p->max_K > KS_MAX_K)) return KS_E_RANGE;
   return KS_OK;
 }
 
-constexpr int kNT = 256;
-constexpr int kRB = 4;
+void free_workspace(ks_ctx* c) {
+  (void)hipFree(c->hdr);
+  (void)hipFree(c->items);
+  (void)hipFree(c->mom_base);
+  (void)hipFree(c->done);
+  (void)hipFree(c->smin);
+  (void)hipFree(c->mom);
+  c->hdr = nullptr;
+  c->items = nullptr;
+  c->mom_base = nullptr;
+  c->done = nullptr;
+  c->smin = nullptr;
+  c->mom = nullptr;
+  c->cap_series = c->cap_rows = 0;
+}
+
+// Grow the workspace to hold num_series series and rows split-series rows.
+int ensure_workspace(ks_ctx* c, uint64_t num_series, uint64_t rows) {
+  if (num_series <= c->cap_series && rows <= c->cap_rows && c->hdr) return KS_OK;
+  const uint64_t ns = num_series > c->cap_series ? num_series : c->cap_series;
+  const uint64_t nr = rows > c->cap_rows ? rows : c->cap_rows;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  free_workspace(c);
+  if (hipMalloc(&c->hdr, 256) != hipSuccess || hipMalloc(&c->items, sizeof(ks::Item) * ks::kMaxChunks * ns) != hipSuccess ||
+      hipMalloc(&c->mom_base, sizeof(uint64_t) * ns) != hipSuccess || hipMalloc(&c->done, sizeof(uint32_t) * ns) != hipSuccess ||
+      hipMalloc(&c->smin, sizeof(uint32_t) * ns) != hipSuccess ||
+      hipMalloc(&c->mom, sizeof(ks::RowMom) * (nr ? nr : 1)) != hipSuccess) {
+    free_workspace(c);
+    (void)hipGetLastError();
+    return KS_E_NOMEM;
+  }
+  c->cap_series = ns;
+  c->cap_rows = nr;
+  return KS_OK;
+}
+
+ks::Workspace workspace_of(const ks_ctx* c) {
+  return ks::Workspace{c->hdr, c->items, c->mom_base, c->done, c->smin, c->mom};
+}
+
+struct ScanArgs {
+  const uint32_t* samples;
+  uint64_t num_samples;
+  const ks_desc* desc;
+  uint32_t num_series;
+  ks_params prm;
+  uint32_t max_K;
+  ks_result* out;
+  uint32_t* allU;
+  uint64_t allU_len;
+  uint32_t chunk;
+  ks::Workspace ws;
+};
 
 template <int KMAX>
-hipError_t launch_scan(const uint32_t* samples, uint64_t num_samples, const ks_desc* desc, uint32_t num_series,
-                       const ks_params& prm, uint32_t max_K, ks_result* out, uint32_t* allU, uint64_t allU_len,
-                       hipStream_t st) {
-  hipLaunchKernelGGL((ks::scan_kernel<KMAX, kNT, kRB>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples,
-                     desc, num_series, prm, max_K, out, allU, allU_len);
+struct Kernels {
+  static const void* grid() { return reinterpret_cast<const void*>(&ks::scan_kernel<KMAX, kNT, kRB>); }
+  static const void* persistent() { return reinterpret_cast<const void*>(&ks::scan_persistent<KMAX, kNT, kRB>); }
+  static const void* finish() { return reinterpret_cast<const void*>(&ks::finish_kernel<KMAX, kNT, kRB>); }
+};
+
+// kind: 0 grid scan, 1 persistent scan, 2 finish
+const void* kernel_for(int kc, int kind) {
+#define KS_KSEL(KM) \
+  return kind == 0 ? Kernels<KM>::grid() : (kind == 1 ? Kernels<KM>::persistent() : Kernels<KM>::finish())
+  switch (kc) {
+    case 0: KS_KSEL(64);
+    case 1: KS_KSEL(128);
+    case 2: KS_KSEL(256);
+    case 3: KS_KSEL(512);
+    case 4: KS_KSEL(1024);
+    default: KS_KSEL(2048);
+  }
+#undef KS_KSEL
+}
+
+template <int KMAX>
+hipError_t launch_grid(const ScanArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((ks::scan_kernel<KMAX, kNT, kRB>), dim3(a.num_series), dim3(kNT), 0, st, a.samples,
+                     a.num_samples, a.desc, a.num_series, a.prm, a.max_K, a.out, a.allU, a.allU_len,
+                     (const uint32_t*)nullptr);
   return hipGetLastError();
+}
+
+hipError_t launch_grid_kc(int kc, const ScanArgs& a, hipStream_t st) {
+  switch (kc) {
+    case 0: return launch_grid<64>(a, st);
+    case 1: return launch_grid<128>(a, st);
+    case 2: return launch_grid<256>(a, st);
+    case 3: return launch_grid<512>(a, st);
+    case 4: return launch_grid<1024>(a, st);
+    default: return launch_grid<2048>(a, st);
+  }
+}
+
+int persistent_grid(ks_ctx* c, int kc, uint32_t& grid) {
+  if (!c->occupancy[kc]) {
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_for(kc, 1), kNT, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    c->occupancy[kc] = nb > 0 ? nb : 1;
+  }
+  grid = (uint32_t)(c->num_cus * c->occupancy[kc]);
+  return KS_OK;
+}
+
+// Launch the plan's kernels (directly, or from a cached hipGraph whose kernel
+// arguments are updated for this call).
+int launch_plan(ks_ctx* c, int kc, int mode, const ScanArgs& a, bool use_graph, hipStream_t st) {
+  ScanArgs v = a;
+  const uint32_t* order = reinterpret_cast<const uint32_t*>(v.ws.items);
+  void* plan_args[] = {&v.desc, &v.num_series, &v.num_samples, &v.max_K, &v.chunk, &v.ws};
+  void* grid_args[] = {&v.samples, &v.num_samples, &v.desc, &v.num_series, &v.prm, &v.max_K,
+                       &v.out, &v.allU, &v.allU_len, &order};
+  void* pers_args[] = {&v.samples, &v.num_samples, &v.desc, &v.num_series, &v.prm, &v.max_K,
+                       &v.out, &v.allU, &v.allU_len, &v.chunk, &v.ws};
+  void* fin_args[] = {&v.num_samples, &v.desc, &v.num_series, &v.prm, &v.max_K, &v.out,
+                      &v.allU, &v.allU_len, &v.chunk, &v.ws};
+  hipKernelNodeParams np[3] = {};
+  int n = 0;
+  np[n].blockDim = dim3(ks::kPlanNT);
+  np[n].gridDim = dim3(1);
+  np[n].func = reinterpret_cast<void*>(&ks::plan_kernel);
+  np[n++].kernelParams = plan_args;
+  uint32_t grid = v.num_series;
+  if (mode == KS_LAUNCH_PERSISTENT) {
+    if (int rc = persistent_grid(c, kc, grid)) return rc;
+    np[n].blockDim = dim3(kNT);
+    np[n].gridDim = dim3(grid);
+    np[n].func = const_cast<void*>(kernel_for(kc, 1));
+    np[n++].kernelParams = pers_args;
+    np[n].blockDim = dim3(kNT);
+    np[n].gridDim = dim3(v.num_series);
+    np[n].func = const_cast<void*>(kernel_for(kc, 2));
+    np[n++].kernelParams = fin_args;
+  } else {
+    np[n].blockDim = dim3(kNT);
+    np[n].gridDim = dim3(v.num_series);
+    np[n].func = const_cast<void*>(kernel_for(kc, 0));
+    np[n++].kernelParams = grid_args;
+  }
+  hipError_t e;
+  if (!use_graph) {
+    for (int i = 0; i < n; ++i) {
+      e = hipLaunchKernel(np[i].func, np[i].gridDim, np[i].blockDim, np[i].kernelParams, 0, st);
+      if (e != hipSuccess) return hip_fail(e, "plan launch");
+    }
+    return KS_OK;
+  }
+  // the graph topology depends on the grid sizes only through the nodes'
+  // parameters, so one graph per (mode, K class, persistent grid) is reused
+  auto key = std::make_tuple(mode, kc, mode == KS_LAUNCH_PERSISTENT ? grid : 0u);
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    GraphEntry g;
+    if ((e = hipGraphCreate(&g.graph, 0)) != hipSuccess) return hip_fail(e, "hipGraphCreate");
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+      e = hipGraphAddKernelNode(&g.node[i], g.graph, i ? &g.node[i - 1] : nullptr, i ? 1 : 0, &np[i]);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g.graph);
+      return hip_fail(e, "graph build");
+    }
+    g.nodes = n;
+    it = c->graphs.emplace(key, g).first;
+  } else {
+    for (int i = 0; i < n; ++i)
+      if ((e = hipGraphExecKernelNodeSetParams(it->second.exec, it->second.node[i], &np[i])) != hipSuccess)
+        return hip_fail(e, "graph update");
+  }
+  if ((e = hipGraphLaunch(it->second.exec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return KS_OK;
+}
+
+LaunchCfg config_for(const ks_ctx* c, int kc, uint32_t num_series, uint32_t opts) {
+  LaunchCfg cfg;
+  auto it = c->tuned.find(std::make_tuple(kc, num_series));
+  if (it != c->tuned.end()) cfg = it->second;
+  if (opts & KS_OPT_GRID) cfg.mode = KS_LAUNCH_GRID;
+  if (opts & KS_OPT_PERSISTENT) cfg.mode = KS_LAUNCH_PERSISTENT;
+  if (opts & KS_OPT_NO_GRAPH) cfg.graph = 0;
+  return cfg;
+}
+
+int scan_with(ks_ctx* ctx, const ScanArgs& a, int kc, const LaunchCfg& cfg, hipStream_t st) {
+  if (cfg.mode == KS_LAUNCH_GRID) {
+    hipError_t e = launch_grid_kc(kc, a, st);
+    return e == hipSuccess ? KS_OK : hip_fail(e, "scan launch");
+  }
+  const bool split = cfg.mode == KS_LAUNCH_PERSISTENT;
+  if (int rc = ensure_workspace(ctx, a.num_series, split ? (uint64_t)a.num_series * a.max_K : 0)) return rc;
+  ScanArgs b = a;
+  b.chunk = split ? cfg.chunk_bytes : 0xffffffffu;  // the ordered grid never splits
+  b.ws = workspace_of(ctx);
+  return launch_plan(ctx, kc, cfg.mode, b, cfg.graph != 0, st);
+}
+
+bool valid_launch(const ks_launch* c) {
+  return c && c->mode <= KS_LAUNCH_ORDERED && c->graph <= 1 && c->chunk_bytes >= 4096u &&
+         c->chunk_bytes <= (1u << 30);
+}
+
+LaunchCfg from_launch(const ks_launch* c) {
+  LaunchCfg l;
+  l.mode = (int)c->mode;
+  l.chunk_bytes = c->chunk_bytes;
+  l.graph = (int)c->graph;
+  return l;
+}
+
+ks_launch to_launch(const LaunchCfg& l) { return ks_launch{(uint32_t)l.mode, l.chunk_bytes, (uint32_t)l.graph, 0}; }
+
+// Tune-cache lines: "<arch> <cus> <kclass> <num_series> <mode> <chunk_bytes> <graph>".
+void load_tune_cache(ks_ctx* c) {
+  const char* path = std::getenv("KS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char arch[128];
+  int cus, kc, pers, graph;
+  unsigned ns, chunk;
+  while (std::fscanf(f, "%127s %d %d %u %d %u %d", arch, &cus, &kc, &ns, &pers, &chunk, &graph) == 7) {
+    ks_launch l{(uint32_t)pers, chunk, (uint32_t)graph, 0};
+    if (c->arch == arch && cus == c->num_cus && kc >= 0 && kc < kNumKClasses && valid_launch(&l))
+      c->tuned[std::make_tuple(kc, (uint32_t)ns)] = from_launch(&l);
+  }
+  std::fclose(f);
+}
+
+void append_tune_cache(const ks_ctx* c, int kc, uint32_t ns, const LaunchCfg& l) {
+  const char* path = std::getenv("KS_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %u %d %u %d\n", c->arch.c_str(), c->num_cus, kc, ns, l.mode, l.chunk_bytes, l.graph);
+  std::fclose(f);
 }
 
 }  // namespace
@@ -110,22 +381,34 @@ int ks_ctx_create(int device, ks_ctx** out) {
   if (!c) return KS_E_NOMEM;
   c->device = device;
   c->num_cus = prop.multiProcessorCount;
-  c->lds_per_block = prop.sharedMemPerBlock;
+  c->arch = prop.gcnArchName;
+  const size_t colon = c->arch.find(':');
+  if (colon != std::string::npos) c->arch.resize(colon);
+  load_tune_cache(c);
   *out = c;
   return KS_OK;
 }
 
 int ks_ctx_destroy(ks_ctx* ctx) {
   if (!ctx) return KS_E_INVALID;
+  {
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->graphs) {
+      (void)hipGraphExecDestroy(kv.second.exec);
+      (void)hipGraphDestroy(kv.second.graph);
+    }
+    free_workspace(ctx);
+  }
   delete ctx;
   return KS_OK;
 }
 
 int ks_reserve(ks_ctx* ctx, uint32_t max_series, uint64_t max_total_steps) {
   if (!ctx) return KS_E_INVALID;
-  ctx->reserved_series = max_series;
-  ctx->reserved_steps = max_total_steps;
-  return KS_OK;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  return ensure_workspace(ctx, max_series, max_total_steps);
 }
 
 int ks_scan_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, const ks_desc* desc,
@@ -139,21 +422,83 @@ int ks_scan_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, co
   DeviceGuard g(ctx->device);
   if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
   const uint32_t max_K = params->max_K ? params->max_K : KS_MAX_K;
+  const int kc = k_class(max_K);
+  ScanArgs a{samples, num_samples, desc, num_series, *params, max_K, out, all_U, all_U_len, 0, {}};
+  return scan_with(ctx, a, kc, config_for(ctx, kc, num_series, params->opts), (hipStream_t)stream);
+}
+
+int ks_launch_set(ks_ctx* ctx, uint32_t max_K, uint32_t num_series, const ks_launch* cfg) {
+  if (!ctx || !cfg) return KS_E_INVALID;
+  if (!valid_launch(cfg)) return KS_E_RANGE;
+  ctx->tuned[std::make_tuple(k_class(max_K ? max_K : KS_MAX_K), num_series)] = from_launch(cfg);
+  return KS_OK;
+}
+
+int ks_launch_get(ks_ctx* ctx, uint32_t max_K, uint32_t num_series, ks_launch* cfg) {
+  if (!ctx || !cfg) return KS_E_INVALID;
+  *cfg = to_launch(config_for(ctx, k_class(max_K ? max_K : KS_MAX_K), num_series, 0));
+  return KS_OK;
+}
+
+int ks_autotune(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, const ks_desc* desc,
+                uint32_t num_series, const ks_params* params, ks_result* out, void* stream, ks_launch* best,
+                float* best_ms) {
+  if (!ctx || !params || !out) return KS_E_INVALID;
+  if (int rc = check_params(params)) return rc;
+  if (num_series == 0) return KS_OK;
+  if (!samples || !desc) return KS_E_INVALID;
+  if (num_series > (1u << 30)) return KS_E_RANGE;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  const uint32_t max_K = params->max_K ? params->max_K : KS_MAX_K;
+  const int kc = k_class(max_K);
   hipStream_t st = (hipStream_t)stream;
+  ScanArgs a{samples, num_samples, desc, num_series, *params, max_K, out, nullptr, 0, 0, {}};
+  LaunchCfg cands[10];
+  int nc = 0;
+  cands[nc++] = LaunchCfg{KS_LAUNCH_GRID, 1u << 20, 0};
+  cands[nc++] = LaunchCfg{KS_LAUNCH_ORDERED, 1u << 20, 1};
+  cands[nc++] = LaunchCfg{KS_LAUNCH_ORDERED, 1u << 20, 0};
+  for (uint32_t chunk : {1u << 20, 4u << 20, 16u << 20}) {
+    cands[nc++] = LaunchCfg{KS_LAUNCH_PERSISTENT, chunk, 1};
+    cands[nc++] = LaunchCfg{KS_LAUNCH_PERSISTENT, chunk, 0};
+  }
+  hipEvent_t e0, e1;
   hipError_t e;
-  if (max_K <= 64)
-    e = launch_scan<64>(samples, num_samples, desc, num_series, *params, max_K, out, all_U, all_U_len, st);
-  else if (max_K <= 128)
-    e = launch_scan<128>(samples, num_samples, desc, num_series, *params, max_K, out, all_U, all_U_len, st);
-  else if (max_K <= 256)
-    e = launch_scan<256>(samples, num_samples, desc, num_series, *params, max_K, out, all_U, all_U_len, st);
-  else if (max_K <= 512)
-    e = launch_scan<512>(samples, num_samples, desc, num_series, *params, max_K, out, all_U, all_U_len, st);
-  else if (max_K <= 1024)
-    e = launch_scan<1024>(samples, num_samples, desc, num_series, *params, max_K, out, all_U, all_U_len, st);
-  else
-    e = launch_scan<2048>(samples, num_samples, desc, num_series, *params, max_K, out, all_U, all_U_len, st);
-  if (e != hipSuccess) return hip_fail(e, "scan launch");
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  int rc = KS_OK, bi = -1;
+  float bms = 0.f;
+  for (int i = 0; i < nc && rc == KS_OK; ++i) {
+    rc = scan_with(ctx, a, kc, cands[i], st);  // warm-up (builds graphs, grows the workspace)
+    float tmin = 0.f;
+    for (int r = 0; r < 3 && rc == KS_OK; ++r) {
+      if ((e = hipEventRecord(e0, st)) != hipSuccess) { rc = hip_fail(e, "hipEventRecord"); break; }
+      rc = scan_with(ctx, a, kc, cands[i], st);
+      if (rc) break;
+      if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+        rc = hip_fail(e, "hipEventSynchronize");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (r == 0 || ms < tmin) tmin = ms;
+    }
+    if (rc == KS_OK && (bi < 0 || tmin < bms)) {
+      bi = i;
+      bms = tmin;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  ctx->tuned[std::make_tuple(kc, num_series)] = cands[bi];
+  append_tune_cache(ctx, kc, num_series, cands[bi]);
+  if (best) *best = to_launch(cands[bi]);
+  if (best_ms) *best_ms = bms;
   return KS_OK;
 }
 

@@ -83,7 +83,7 @@ __device__ __forceinline__ bool more_significant(uint32_t Ua, uint32_t a, uint32
 // Asymptotic Kolmogorov tail from lambda^2: the alternating exp(-2 k^2 l^2)
 // series for lambda >= 1, the Jacobi-theta form below; each stops once a term
 // is under 1e-20 of the sum; 0 once 2 lambda^2 > 700.
-__device__ double kolmogorov_q(double lambda2) {
+__device__ __noinline__ double kolmogorov_q(double lambda2) {
   if (!(lambda2 > 0.0)) return 1.0;
   if (2.0 * lambda2 > 700.0) return 0.0;
   double sum = 0.0;
@@ -121,68 +121,164 @@ __device__ __forceinline__ void write_result(ks_result* o, uint32_t cp, uint32_t
 
 // ---------------------------------------------------------------- phases
 
-// Phase 1: per-row moments into LDS; returns the series minimum (block-uniform).
-template <int KMAX, int NT, int RB>
-__device__ uint32_t stream_moments(ScanSmem<KMAX, NT, RB>& sm, const uint32_t* __restrict__ base, uint32_t K,
-                                   uint32_t N, bool vec4) {
-  using S = ScanShape<KMAX, NT, RB>;
-  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
-  uint32_t mn = 0xffffffffu;
-  for (uint32_t i = w; i < K; i += S::W) {
-    const uint32_t* row = base + (uint64_t)i * N;
-    uint64_t s1 = 0, s2 = 0;
-    uint32_t s2h = 0;
-    if (vec4) {
-      const u32x4* r4 = reinterpret_cast<const u32x4*>(row);
-      const uint32_t n4 = N >> 2;
-      uint32_t q = lane;
-      for (; q + 3 * kWave < n4; q += 4 * kWave) {
-        const u32x4 a = __builtin_nontemporal_load(r4 + q);
-        const u32x4 b = __builtin_nontemporal_load(r4 + q + kWave);
-        const u32x4 c = __builtin_nontemporal_load(r4 + q + 2 * kWave);
-        const u32x4 d = __builtin_nontemporal_load(r4 + q + 3 * kWave);
-        acc_sample(a.x, mn, s1, s2, s2h); acc_sample(a.y, mn, s1, s2, s2h);
-        acc_sample(a.z, mn, s1, s2, s2h); acc_sample(a.w, mn, s1, s2, s2h);
-        acc_sample(b.x, mn, s1, s2, s2h); acc_sample(b.y, mn, s1, s2, s2h);
-        acc_sample(b.z, mn, s1, s2, s2h); acc_sample(b.w, mn, s1, s2, s2h);
-        acc_sample(c.x, mn, s1, s2, s2h); acc_sample(c.y, mn, s1, s2, s2h);
-        acc_sample(c.z, mn, s1, s2, s2h); acc_sample(c.w, mn, s1, s2, s2h);
-        acc_sample(d.x, mn, s1, s2, s2h); acc_sample(d.y, mn, s1, s2, s2h);
-        acc_sample(d.z, mn, s1, s2, s2h); acc_sample(d.w, mn, s1, s2, s2h);
+// ---------------------------------------------------------------- streaming
+//
+// A wave streams its rows in batches: per lane up to four 16-byte loads of the
+// row's 16-byte-aligned body (1024 samples per wave-batch), plus, in a row's
+// last batch, one dword of the unaligned head or tail (lanes 0..2 / 32..34).
+// The next batch is loaded before the current one is accumulated, so one
+// batch per wave stays in flight while the wave computes; a row's sums are
+// reduced with DPP once its last batch is in.
+
+struct RowGeo {
+  uint64_t e0;    // first sample of the row (element index from `samples`)
+  uint32_t head;  // samples before the first 16-byte boundary
+  uint32_t nq;    // 16-byte quads of the aligned body
+  uint32_t tail;  // samples after the body
+  uint32_t nb;    // batches (>= 1)
+};
+
+__device__ __forceinline__ RowGeo row_geo(const uint32_t* samples, uint64_t e0, uint32_t N) {
+  RowGeo g;
+  g.e0 = e0;
+  const uint32_t a = (uint32_t)(((uintptr_t)(samples + e0) >> 2) & 3u);
+  g.head = a ? min(4u - a, N) : 0u;
+  g.nq = (N - g.head) >> 2;
+  g.tail = (N - g.head) & 3u;
+  g.nb = g.nq ? (g.nq + 4 * kWave - 1) / (4 * kWave) : 1u;
+  return g;
+}
+
+struct Batch {
+  u32x4 q[4];
+  uint32_t x;
+  uint32_t m;  // bit u: q[u] holds data; bit 4: x holds data
+};
+
+__device__ __forceinline__ void load_batch(Batch& B, const uint32_t* __restrict__ samples, const RowGeo& g,
+                                           uint32_t b, uint32_t lane) {
+  const u32x4* body = reinterpret_cast<const u32x4*>(samples + g.e0 + g.head);
+  const uint32_t q0 = b * (4 * kWave) + lane;
+  uint32_t m = 0;
+  if (b * (4 * kWave) + 4 * kWave <= g.nq) {  // full batch (wave-uniform)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) B.q[u] = __builtin_nontemporal_load(body + q0 + u * kWave);
+    m = 15u;
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (q0 + u * kWave < g.nq) {
+        B.q[u] = __builtin_nontemporal_load(body + q0 + u * kWave);
+        m |= 1u << u;
+      } else {
+        B.q[u] = u32x4{0u, 0u, 0u, 0u};
       }
-      for (; q < n4; q += kWave) {
-        const u32x4 a = __builtin_nontemporal_load(r4 + q);
-        acc_sample(a.x, mn, s1, s2, s2h); acc_sample(a.y, mn, s1, s2, s2h);
-        acc_sample(a.z, mn, s1, s2, s2h); acc_sample(a.w, mn, s1, s2, s2h);
-      }
-    } else {
-      uint32_t q = lane;
-      for (; q + 3 * kWave < N; q += 4 * kWave) {
-        const uint32_t a = __builtin_nontemporal_load(row + q);
-        const uint32_t b = __builtin_nontemporal_load(row + q + kWave);
-        const uint32_t c = __builtin_nontemporal_load(row + q + 2 * kWave);
-        const uint32_t d = __builtin_nontemporal_load(row + q + 3 * kWave);
-        acc_sample(a, mn, s1, s2, s2h); acc_sample(b, mn, s1, s2, s2h);
-        acc_sample(c, mn, s1, s2, s2h); acc_sample(d, mn, s1, s2, s2h);
-      }
-      for (; q < N; q += kWave) acc_sample(__builtin_nontemporal_load(row + q), mn, s1, s2, s2h);
-    }
-    s1 = wave_sum_u64(s1);
-    wave_sum_u96(s2, s2h);
-    if (lane == 0) {
-      sm.u.mom.s1[i] = s1;
-      sm.u.mom.s2lo[i] = s2;
-      sm.u.mom.s2hi[i] = s2h;
     }
   }
-  mn = wave_min_u32(mn);
-  if (lane == 0) sm.red[w] = mn;
-  __syncthreads();
-  uint32_t g = sm.red[0];
+  B.x = 0;
+  if (b + 1 == g.nb) {
+    if (lane < g.head) {
+      B.x = __builtin_nontemporal_load(samples + g.e0 + lane);
+      m |= 16u;
+    } else if (lane >= 32 && lane - 32 < g.tail) {
+      B.x = __builtin_nontemporal_load(samples + g.e0 + g.head + 4ull * g.nq + (lane - 32));
+      m |= 16u;
+    }
+  }
+  B.m = m;
+}
+
+__device__ __forceinline__ void acc_quad(const u32x4& v, uint32_t& mn, uint64_t& s1, uint64_t& s2, uint32_t& s2h) {
+  acc_sample(v.x, mn, s1, s2, s2h);
+  acc_sample(v.y, mn, s1, s2, s2h);
+  acc_sample(v.z, mn, s1, s2, s2h);
+  acc_sample(v.w, mn, s1, s2, s2h);
+}
+
+__device__ __forceinline__ void acc_batch(const Batch& B, uint32_t& mn, uint64_t& s1, uint64_t& s2, uint32_t& s2h) {
+  if ((B.m & 15u) == 15u) {
 #pragma unroll
-  for (int v = 1; v < S::W; ++v) g = min(g, sm.red[v]);
+    for (int u = 0; u < 4; ++u) acc_quad(B.q[u], mn, s1, s2, s2h);
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (B.m & (1u << u)) acc_quad(B.q[u], mn, s1, s2, s2h);
+  }
+  if (B.m & 16u) acc_sample(B.x, mn, s1, s2, s2h);
+}
+
+// Streams rows rb, rb + step, ... < re of the series whose row i starts at
+// samples[off + i N]. For each row, emit(i, s1, s2lo, s2hi) receives the
+// wave-uniform totals (sum r, sum r^2). Returns this lane's running minimum.
+template <typename Emit>
+__device__ __forceinline__ uint32_t stream_rows(const uint32_t* __restrict__ samples, uint64_t off, uint32_t N,
+                                                uint32_t rb, uint32_t re, uint32_t step, uint32_t lane,
+                                                Emit&& emit) {
+  uint32_t mn = 0xffffffffu;
+  if (rb >= re) return mn;
+  uint32_t row = rb, b = 0;
+  RowGeo g = row_geo(samples, off + (uint64_t)row * N, N);
+  Batch cur, nxt;
+  load_batch(cur, samples, g, 0, lane);
+  uint64_t s1 = 0, s2 = 0;
+  uint32_t s2h = 0;
+  for (;;) {
+    uint32_t nrow = row, nbb = b + 1;
+    RowGeo ng = g;
+    if (nbb == g.nb) {
+      nrow = row + step;
+      nbb = 0;
+      if (nrow < re) ng = row_geo(samples, off + (uint64_t)nrow * N, N);
+    }
+    const bool more = nrow < re;
+    if (more) load_batch(nxt, samples, ng, nbb, lane);
+    acc_batch(cur, mn, s1, s2, s2h);
+    if (b + 1 == g.nb) {
+      wave_total_64_96(s1, s2, s2h);
+      emit(row, s1, s2, s2h);
+      s1 = 0;
+      s2 = 0;
+      s2h = 0;
+    }
+    if (!more) break;
+    cur = nxt;
+    row = nrow;
+    b = nbb;
+    g = ng;
+  }
+  return mn;
+}
+
+// Block-wide minimum of a per-lane value (all threads get it).
+template <int NT>
+__device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t* red) {
+  constexpr int W = NT / kWave;
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  v = wave_min_u32(v);
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  uint32_t g = red[0];
+#pragma unroll
+  for (int k = 1; k < W; ++k) g = min(g, red[k]);
   __syncthreads();
   return g;
+}
+
+// Phase 1: per-row moments into LDS; returns the series minimum (block-uniform).
+template <int KMAX, int NT, int RB>
+__device__ uint32_t stream_moments(ScanSmem<KMAX, NT, RB>& sm, const uint32_t* __restrict__ samples, uint64_t off,
+                                   uint32_t K, uint32_t N) {
+  using S = ScanShape<KMAX, NT, RB>;
+  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t mn = stream_rows(samples, off, N, w, K, S::W, lane,
+                                  [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h) {
+                                    if (lane == 0) {
+                                      sm.u.mom.s1[i] = s1;
+                                      sm.u.mom.s2lo[i] = s2;
+                                      sm.u.mom.s2hi[i] = s2h;
+                                    }
+                                  });
+  return block_min_u32<NT>(mn, sm.red);
 }
 
 // Phase 2: Q_i keys (ping buffer) and their OR (for the number of radix passes).
@@ -388,21 +484,23 @@ __device__ void scan_one(ScanSmem<KMAX, NT, RB>& sm, const uint32_t* __restrict_
     if (threadIdx.x == 0) write_result(out, 0, 0, 0, 0, 0.0, 0.0, 1.0, bad);
     return;
   }
-  const uint32_t* base = samples + d.offset;
-  const bool vec4 = ((d.offset | d.N) & 3u) == 0 && ((uintptr_t)samples & 15u) == 0;
-  const uint32_t gmin = stream_moments(sm, base, d.K, d.N, vec4);
+  const uint32_t gmin = stream_moments(sm, samples, d.offset, d.K, d.N);
   const bool fits = allU && d.aux_offset <= allU_len && d.K <= allU_len - d.aux_offset;
   finish_series(sm, d.K, d.N, gmin, prm, out, fits ? allU + d.aux_offset : nullptr);
 }
 
-// One workgroup per series.
+// One workgroup per series; with `order`, workgroup b takes series order[b]
+// (the plan's largest-first order, one item per series, 8-byte items whose
+// first word is the series).
 template <int KMAX, int NT, int RB>
 __global__ __launch_bounds__(NT) void scan_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                   const ks_desc* __restrict__ desc, uint32_t num_series,
                                                   ks_params prm, uint32_t max_K, ks_result* __restrict__ out,
-                                                  uint32_t* __restrict__ allU, uint64_t allU_len) {
+                                                  uint32_t* __restrict__ allU, uint64_t allU_len,
+                                                  const uint32_t* __restrict__ order) {
   __shared__ ScanSmem<KMAX, NT, RB> sm;
-  const uint32_t s = blockIdx.x;
+  if (blockIdx.x >= num_series) return;
+  const uint32_t s = order ? __builtin_amdgcn_readfirstlane(order[2 * blockIdx.x]) : blockIdx.x;
   if (s >= num_series) return;
   const ks_desc d = desc[s];
   scan_one(sm, samples, num_samples, d, prm, max_K, out + s, allU, allU_len);

@@ -1,0 +1,78 @@
+"""Full-size batches in the launch configuration bench.py times (default plan).
+
+Every series is checked against properties that hold at any size; a seeded
+sample of series is copied back and recomputed one by one by the oracle
+(bit-exact fields, p within 1e-12).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2511_05958_amd as P
+from paper_2511_05958_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+def run_full(recipe, sample_count, seed):
+    import torch
+
+    b = S.make_batch(recipe)
+    n = b.num_series
+    buf = torch.empty(b.total_elems, dtype=torch.int32, device="cuda")
+    S.fill_device(b, buf.data_ptr(), b.total_elems)
+    d = P.make_desc(b.specs["offset"], b.specs["K"], b.specs["N"])
+    prm = P.ks_params_init(0.05)
+    prm.max_K = int(d["K"].max())
+    out = P.empty_results(n)
+    with P.Context(0) as ctx:
+        P.ks_scan_batch(ctx.handle, buf, P.to_device(d), n, prm, out)
+        torch.cuda.synchronize()
+    g = P.results_to_numpy(out)
+
+    # properties of every series
+    K = d["K"].astype(np.int64)
+    cp, nn, mm, U = (g[f].astype(np.int64) for f in ("cp", "n", "m", "U"))
+    assert (g["flags"] & (P.KS_BAD_SHAPE | P.KS_OUT_OF_RANGE) == 0).all()
+    assert ((cp >= 1) & (cp < K) & (nn == cp) & (mm == K - cp)).all()
+    assert (U <= nn * mm).all()
+    assert np.array_equal(g["D"], U / (nn * mm))
+    lam2 = (U * U).astype(np.float64) / (nn * mm * K).astype(np.float64)
+    assert np.array_equal(g["lambda"], np.sqrt(lam2))
+    sig = (U * U).astype(np.float64) > prm.c_alpha * (nn * mm * K).astype(np.float64)
+    assert np.array_equal((g["flags"] & P.KS_SIGNIFICANT) != 0, sig)
+    assert ((g["p"] >= 0) & (g["p"] <= 1)).all()
+
+    # a seeded sample recomputed by the oracle
+    rng = np.random.default_rng(seed)
+    pick = np.sort(rng.choice(n, size=min(sample_count, n), replace=False))
+    for t in pick:
+        o0, k, nn_ = int(d[t]["offset"]), int(d[t]["K"]), int(d[t]["N"])
+        r = buf[o0:o0 + k * nn_].cpu().numpy().view(np.uint32).reshape(k, nn_)
+        o = O.scan_series(r)
+        assert (g[t]["cp"], g[t]["U"], g[t]["n"], g[t]["m"]) == (o["cp"], o["U"], o["n"], o["m"]), t
+        assert g[t]["D"] == o["D"] and g[t]["lambda"] == o["lambda"]
+        assert bool(g[t]["flags"] & P.KS_SIGNIFICANT) == bool(o["significant"])
+        assert g[t]["p"] == o["p"] or abs(g[t]["p"] - o["p"]) <= 1e-12 * abs(o["p"]), t
+    del buf
+    torch.cuda.empty_cache()
+    return g
+
+
+def test_recipe2_full_4096_series():
+    g = run_full(2, 32, 2)
+    assert len(g) == 4096
+
+
+def test_recipe3_full_16384_uneven_series():
+    g = run_full(3, 48, 3)
+    assert len(g) == 16384
+
+
+def test_recipe5_full_8192_series():
+    g = run_full(5, 8, 5)
+    assert len(g) == 8192
+    assert math.isfinite(float(g["lambda"].max()))

@@ -24,12 +24,20 @@ def ctx(dev):
     c.close()
 
 
-def run_gpu(ctx, samples, desc, alpha=0.05, max_K=0, allU_len=None, num_samples=None):
+DEFAULT_LAUNCH = (P.KS_LAUNCH_ORDERED, 1 << 20, 1)
+LAUNCHES = [(P.KS_LAUNCH_GRID, 1 << 20, 0), (P.KS_LAUNCH_ORDERED, 1 << 20, 1), (P.KS_LAUNCH_ORDERED, 1 << 20, 0),
+            (P.KS_LAUNCH_PERSISTENT, 1 << 20, 1), (P.KS_LAUNCH_PERSISTENT, 64 << 10, 1),
+            (P.KS_LAUNCH_PERSISTENT, 16 << 10, 0)]
+LAUNCH_IDS = ["grid", "ordered-graph", "ordered-direct", "persistent", "split64k-graph", "split16k-direct"]
+
+
+def run_gpu(ctx, samples, desc, alpha=0.05, max_K=0, allU_len=None, num_samples=None, launch=None):
     import torch
 
     n = len(desc)
     prm = P.ks_params_init(alpha)
     prm.max_K = max_K
+    P.ks_launch_set(ctx.handle, max_K, n, *(launch or DEFAULT_LAUNCH))
     s_d = P.to_device(samples) if len(samples) else torch.zeros(1, dtype=torch.int32, device="cuda")
     d_d = P.to_device(desc) if n else torch.zeros(24, dtype=torch.uint8, device="cuda")
     out = P.empty_results(max(n, 1))
@@ -66,14 +74,44 @@ def batch_arrays(b):
     return x, d
 
 
+@pytest.mark.parametrize("launch", LAUNCHES, ids=LAUNCH_IDS)
 @pytest.mark.parametrize("recipe,num", [(1, 1), (2, 48), (3, 160), (5, 6)])
-def test_parity_recipes(ctx, recipe, num):
+def test_parity_recipes(ctx, recipe, num, launch):
     b = S.make_batch(recipe, num_series=num)
     x, d = batch_arrays(b)
     max_K = int(d["K"].max())
-    g, gU = run_gpu(ctx, x, d, max_K=max_K)
+    g, gU = run_gpu(ctx, x, d, max_K=max_K, launch=launch)
     o, oU, _ = oracle_batch(x, d)
     assert_parity(g, gU, o, oU, d)
+
+
+def test_graph_replay_with_new_buffers(ctx):
+    # same shape (so the cached graph is reused and its arguments updated), different data
+    for first in (0, 40, 80):
+        b = S.make_batch(3, num_series=40, first_series=first)
+        x, d = batch_arrays(b)
+        for ln in (LAUNCHES[1], LAUNCHES[4]):
+            g, gU = run_gpu(ctx, x, d, max_K=512, launch=ln)
+            o, oU, _ = oracle_batch(x, d)
+            assert_parity(g, gU, o, oU, d)
+
+
+def test_autotune_then_scan(ctx):
+    import torch
+
+    b = S.make_batch(3, num_series=64, first_series=1000)
+    x, d = batch_arrays(b)
+    prm = P.ks_params_init(0.05)
+    prm.max_K = 512
+    s_d, d_d, out = P.to_device(x), P.to_device(d), P.empty_results(len(d))
+    best, ms = P.ks_autotune(ctx.handle, s_d, d_d, len(d), prm, out)
+    assert best.mode in (0, 1, 2) and ms > 0
+    got = P.ks_launch_get(ctx.handle, 512, len(d))
+    assert (got.mode, got.chunk_bytes, got.graph) == (best.mode, best.chunk_bytes, best.graph)
+    torch.cuda.synchronize()
+    o, oU, _ = oracle_batch(x, d)
+    g = P.results_to_numpy(out)
+    assert np.array_equal(g["cp"], o["cp"]) and np.array_equal(g["U"], o["U"])
 
 
 def test_parity_recipe1_many_draws(ctx):
@@ -84,7 +122,8 @@ def test_parity_recipe1_many_draws(ctx):
     assert_parity(g, gU, o, oU, d)
 
 
-def test_parity_all_K_variants_and_alpha(ctx):
+@pytest.mark.parametrize("launch", [LAUNCHES[0], LAUNCHES[1], LAUNCHES[5]], ids=["grid", "ordered", "split16k-direct"])
+def test_parity_all_K_variants_and_alpha(ctx, launch):
     # one launch per LDS variant, K at the top of each class
     rng = np.random.default_rng(7)
     for K in (64, 128, 256, 512, 1024, 2048):
@@ -101,12 +140,13 @@ def test_parity_all_K_variants_and_alpha(ctx):
         x = np.concatenate(parts)
         d = P.make_desc(offs, [K] * len(Ns), Ns)
         for alpha in (0.05, 0.001):
-            g, gU = run_gpu(ctx, x, d, alpha=alpha, max_K=K)
+            g, gU = run_gpu(ctx, x, d, alpha=alpha, max_K=K, launch=launch)
             o, oU, _ = oracle_batch(x, d, alpha=alpha)
             assert_parity(g, gU, o, oU, d)
 
 
-def test_edge_cases(ctx):
+@pytest.mark.parametrize("launch", LAUNCHES, ids=LAUNCH_IDS)
+def test_edge_cases(ctx, launch):
     rng = np.random.default_rng(11)
     series = []
     series.append(np.array([[5], [9]], np.uint32))                       # K=2, N=1
@@ -130,17 +170,18 @@ def test_edge_cases(ctx):
         off += 1 + r.size
     x = np.concatenate(parts)
     d = P.make_desc(offs, [r.shape[0] for r in series], [r.shape[1] for r in series])
-    g, gU = run_gpu(ctx, x, d, max_K=512)
+    g, gU = run_gpu(ctx, x, d, max_K=512, launch=launch)
     o, oU, _ = oracle_batch(x, d)
     assert_parity(g, gU, o, oU, d)
     assert g[1]["cp"] == 1 and g[1]["U"] == 0 and g[1]["p"] == 1.0
     assert g[5]["cp"] == 40
 
 
-def test_bad_shapes_and_ranges(ctx):
+@pytest.mark.parametrize("launch", LAUNCHES, ids=LAUNCH_IDS)
+def test_bad_shapes_and_ranges(ctx, launch):
     x = np.arange(1000, dtype=np.uint32)
     d = P.make_desc([0, 0, 0, 0, 990, 2**40, 0], [1, 2, 600, 10, 2, 2, 2], [5, 0, 1, 10, 6, 1, 1])
-    g, gU = run_gpu(ctx, x, d, max_K=512)
+    g, gU = run_gpu(ctx, x, d, max_K=512, launch=launch)
     err = g["flags"] & (P.KS_BAD_SHAPE | P.KS_OUT_OF_RANGE)
     assert list(err[:4]) == [P.KS_BAD_SHAPE, P.KS_BAD_SHAPE, P.KS_BAD_SHAPE, 0]
     assert list(err[4:6]) == [P.KS_OUT_OF_RANGE, P.KS_OUT_OF_RANGE]
@@ -185,9 +226,9 @@ def test_host_validation(ctx):
 def test_deterministic(ctx):
     b = S.make_batch(3, num_series=64, first_series=500)
     x, d = batch_arrays(b)
-    g1, u1 = run_gpu(ctx, x, d, max_K=512)
-    g2, u2 = run_gpu(ctx, x, d, max_K=512)
-    assert g1.tobytes() == g2.tobytes() and np.array_equal(u1, u2)
+    runs = [run_gpu(ctx, x, d, max_K=512, launch=ln) for ln in LAUNCHES + [LAUNCHES[4]]]
+    for g, u in runs[1:]:
+        assert g.tobytes() == runs[0][0].tobytes() and np.array_equal(u, runs[0][1])
 
 
 def test_device_generator_matches_host(dev):
