@@ -16,6 +16,10 @@ cites the passage it restates:
 * ``scan_series``    every index a candidate, the most significant one chosen,
                      eq. 1 significance, p-value as confidence (workflow step 4)
 * ``kolmogorov``     the asymptotic distribution behind eq. 1
+* ``features``       per-row decile features of the learned proposal
+                     (project-defined; minimum as in eq. 2)
+* ``cnn``            the proposal network, forward / backward / Adam in FP64
+                     with BF16 operand rounding (project-defined)
 """
 
 from __future__ import annotations
@@ -57,6 +61,8 @@ def _load():
         lib.oracle_kolmogorov.restype = ctypes.c_double
         lib.oracle_scan_series.argtypes = [vp, u32, u32, ctypes.c_double, vp, vp]
         lib.oracle_scan_batch.argtypes = [vp, vp, vp, vp, u32, ctypes.c_double, vp, vp, vp, ctypes.c_int]
+        lib.oracle_features.argtypes = [vp, u32, u32, vp]
+        lib.oracle_features.restype = None
         assert lib.oracle_result_size() == 48
         _lib = lib
     return _lib
@@ -103,6 +109,46 @@ def scan_series(r, alpha: float = 0.05, want_allU: bool = False):
     allU = np.zeros(max(K, 1), np.uint32)
     _load().oracle_scan_series(r.ctypes.data, K, N, alpha, res.ctypes.data, allU.ctypes.data)
     return (res, allU) if want_allU else res
+
+
+def features(r) -> np.ndarray:
+    """Per-row decile features [K][9] (float32) of one [K][N] series."""
+    r = _u32(r)
+    K, N = r.shape
+    out = np.zeros((K, 9), np.float32)
+    _load().oracle_features(r.ctypes.data, K, N, out.ctypes.data)
+    return out
+
+
+def result_fields(K: int, c: int, U: int, alpha: float = 0.05) -> dict:
+    """The reported fields of choice c with numerator U (same arithmetic as scan_series)."""
+    n, m = c, K - c
+    U2 = float(U * U)
+    nmK = float(n * m * K)
+    lam2 = U2 / nmK
+    return {"cp": c, "n": n, "m": m, "U": U, "D": U / float(n * m), "lambda": float(np.sqrt(lam2)),
+            "p": 1.0 if U == 0 else kolmogorov(lam2), "significant": int(U2 > c_alpha(alpha) * nmK)}
+
+
+def refine(allU, K: int, proposal: int, confidence: float, w: int, tau: float, alpha: float = 0.05) -> dict:
+    """Exact choice restricted to candidates within +-w of the proposal when confidence >= tau,
+    over every candidate otherwise (fallback). allU[c] = U_c of the series (from scan_series).
+    The choice is the most significant candidate of the range (largest U_c^2 / (c (K - c)),
+    compared exactly), ties to the smaller c."""
+    refined = bool(np.float32(confidence) >= np.float32(tau))
+    if refined:
+        lo, hi = max(1, proposal - w), min(K - 1, proposal + w)
+        if lo > hi:  # a proposal outside 1..K-1 leaves an empty window: fall back
+            refined, lo, hi = False, 1, K - 1
+    else:
+        lo, hi = 1, K - 1
+    best = lo
+    for c in range(lo + 1, hi + 1):
+        if int(allU[c]) ** 2 * (best * (K - best)) > int(allU[best]) ** 2 * (c * (K - c)):
+            best = c
+    out = result_fields(K, best, int(allU[best]), alpha)
+    out["refined"] = refined
+    return out
 
 
 def scan_batch(samples, offsets, Ks, Ns, alpha: float = 0.05, threads: int | None = None,

@@ -247,3 +247,32 @@ int oracle_scan_batch(const uint32_t *samples, const uint64_t *offsets, const ui
 }
 
 unsigned oracle_result_size(void) { return (unsigned)sizeof(oracle_result); }
+
+/* ---- learned-proposal inputs (project-defined; the paper has no learned stage) ----
+ *
+ * Per-row quantile features: for each row i, the row's N samples sorted
+ * ascending, the order statistics x_(floor(k (N-1) / 10)) for k = 1..9 (the
+ * nine deciles), each mapped to f = (float)((double)(x - m) / max(m, 1)) with
+ * m the minimum of the whole 2-D array (the eq. 2 global minimum). */
+
+static int cmp_u32(const void *a, const void *b) {
+  uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+void oracle_features(const uint32_t *r, uint32_t K, uint32_t N, float *out /* K*9 */) {
+  uint32_t mn = 0xffffffffu;
+  for (uint64_t t = 0; t < (uint64_t)K * N; ++t)
+    if (r[t] < mn) mn = r[t];
+  const double denom = (double)(mn > 1 ? mn : 1);
+  uint32_t *row = malloc(sizeof(uint32_t) * (N ? N : 1));
+  for (uint32_t i = 0; i < K; ++i) {
+    memcpy(row, r + (uint64_t)i * N, sizeof(uint32_t) * N);
+    qsort(row, N, sizeof(uint32_t), cmp_u32);
+    for (uint32_t k = 1; k <= 9; ++k) {
+      uint32_t x = row[(uint64_t)k * (N - 1) / 10];
+      out[(uint64_t)i * 9 + (k - 1)] = (float)((double)(x - mn) / denom);
+    }
+  }
+  free(row);
+}
