@@ -210,6 +210,89 @@ int ks_autotune(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, cons
                 uint32_t num_series, const ks_params *params, ks_result *out, void *stream, ks_launch *best,
                 float *best_ms);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal (not in the paper: the paper notes that candidate change
+ * points could be shortlisted to save work and skips it because its data are
+ * small; workflow step 4, last paragraph). A small network proposes the
+ * change point of each series from per-row decile features; the exact K-S
+ * choice then runs only within +-w rows of the proposal (ks_refine), or over
+ * all candidates when the proposal's confidence is below tau.
+ *
+ * Network: conv(9->64) ReLU, conv(64->64) ReLU, conv(64->64) ReLU,
+ * conv(64->1), kernel 5, zero padding 2, bias; one logit per row; bf16
+ * operands on the matrix cores with fp32 accumulation. Parameters
+ * (KS_CNN_PARAMS fp32 values, in this order): W0[64][9][5] b0[64]
+ * W1[64][64][5] b1[64] W2[64][64][5] b2[64] W3[1][64][5] b3[1].
+ * Features: for row i the nine deciles x_(floor(k (N-1)/10)), k = 1..9, of
+ * the row's samples, f = (double)(x - m) / max(m, 1) rounded to float, m the
+ * series minimum; layout float[row][9] with series s at rows aux_offset.. .
+ * ------------------------------------------------------------------------ */
+
+#define KS_CNN_PARAMS 44353u
+#define KS_FEATURE_MAX_N 4096u /* largest N the feature pass accepts */
+
+typedef struct ks_model ks_model;
+
+/* Create a model on ctx's device: He-uniform weights drawn from `seed`
+ * (splitmix64), zero biases, zero Adam state. */
+int ks_model_create(ks_ctx *ctx, uint64_t seed, ks_model **out);
+int ks_model_destroy(ks_model *model);
+
+/* Copy the master parameters in (host float[KS_CNN_PARAMS]; resets the Adam
+ * state and step; KS_E_MODEL on a non-finite value) or out. */
+int ks_model_set_params(ks_model *model, const float *params);
+int ks_model_get_params(ks_model *model, float *params);
+
+/* Host copy of the gradient computed by the last ks_train_step (same layout). */
+int ks_model_grads(ks_model *model, float *grads);
+
+/* Checkpoint file: "KSCNN001", parameter count, step, parameters, both Adam
+ * moments, FNV-1a 64 checksum. ks_model_load returns KS_E_MODEL on a bad
+ * magic, size or checksum. Synchronous. */
+int ks_model_save(ks_model *model, const char *path);
+int ks_model_load(ks_model *model, const char *path);
+
+/* Feature pass: per-row moments kept in the context (for ks_refine) and
+ * decile features, written to `features` (device, nullable, float[rows][9],
+ * series s at rows aux_offset .. aux_offset + K - 1 when they fit in
+ * feature_rows). Series with K > max_K (0 = KS_MAX_K), N > KS_FEATURE_MAX_N
+ * or a bad shape / range are skipped. */
+int ks_features(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, const ks_desc *desc,
+                uint32_t num_series, uint32_t max_K, float *features, uint64_t feature_rows, void *stream);
+
+/* Network forward on caller features (device float[feature_rows][9] at
+ * aux_offset): logits (device float[logit_rows], row aux_offset + t). */
+int ks_cnn_forward(ks_ctx *ctx, const ks_model *model, const float *features, uint64_t feature_rows,
+                   const ks_desc *desc, uint32_t num_series, uint32_t max_K, float *logits, uint64_t logit_rows,
+                   void *stream);
+
+/* Proposal: the feature pass, the network, then per series
+ * proposal[s] = argmax of the logits over rows 1..K-1 (smallest on ties) and
+ * confidence[s] = softmax mass of the rows within +-params->w of it (device
+ * int32 / float arrays of num_series). Skipped series get proposal 0,
+ * confidence 0. features: as ks_features (nullable). */
+int ks_propose(ks_ctx *ctx, const ks_model *model, const uint32_t *samples, uint64_t num_samples,
+               const ks_desc *desc, uint32_t num_series, const ks_params *params, int32_t *proposal,
+               float *confidence, float *features, uint64_t feature_rows, void *stream);
+
+/* Exact refine after ks_propose (or ks_features) on the same stream with the
+ * same desc pointer, num_series and max_K (else KS_E_STATE): for each series
+ * the full scan's choice restricted to candidates max(1, p-w) .. min(K-1, p+w)
+ * when confidence >= tau (flag KS_REFINED), or over all candidates otherwise
+ * (KS_FALLBACK; also for a NaN confidence or an empty window). Reads only the
+ * moments kept by the feature pass, not the samples. num_samples as given to
+ * that pass (for the same shape / range checks). */
+int ks_refine(ks_ctx *ctx, const ks_desc *desc, uint32_t num_series, uint64_t num_samples, const int32_t *proposal,
+              const float *confidence, const ks_params *params, ks_result *out, void *stream);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected, fp32 master
+ * weights, bf16 copies rebuilt) on the mean softmax cross-entropy over rows
+ * 1..K-1 of the series whose label (device int32[num_series]) is >= 1; label
+ * -1 skips a series. features as ks_cnn_forward. loss: device float, nullable
+ * (the batch's mean loss before the update). */
+int ks_train_step(ks_ctx *ctx, ks_model *model, const float *features, uint64_t feature_rows, const ks_desc *desc,
+                  const int32_t *labels, uint32_t num_series, uint32_t max_K, float lr, float *loss, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

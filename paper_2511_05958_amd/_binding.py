@@ -18,6 +18,8 @@ _LIB_PATH = Path(__file__).resolve().parent / "libks.so"
 KS_VERSION = 10000
 KS_MAX_K = 2048
 KS_MAX_N = 1 << 24
+KS_CNN_PARAMS = 44353
+KS_FEATURE_MAX_N = 4096
 
 KS_OK = 0
 KS_E_INVALID = -1
@@ -86,6 +88,18 @@ _SIGNATURES = {
     "ks_launch_set": ([_vp, _u32, _u32, _vp], ctypes.c_int),
     "ks_launch_get": ([_vp, _u32, _u32, _vp], ctypes.c_int),
     "ks_autotune": ([_vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "ks_model_create": ([_vp, _u64, _vp], ctypes.c_int),
+    "ks_model_destroy": ([_vp], ctypes.c_int),
+    "ks_model_set_params": ([_vp, _vp], ctypes.c_int),
+    "ks_model_get_params": ([_vp, _vp], ctypes.c_int),
+    "ks_model_grads": ([_vp, _vp], ctypes.c_int),
+    "ks_model_save": ([_vp, ctypes.c_char_p], ctypes.c_int),
+    "ks_model_load": ([_vp, ctypes.c_char_p], ctypes.c_int),
+    "ks_features": ([_vp, _vp, _u64, _vp, _u32, _u32, _vp, _u64, _vp], ctypes.c_int),
+    "ks_cnn_forward": ([_vp, _vp, _vp, _u64, _vp, _u32, _u32, _vp, _u64, _vp], ctypes.c_int),
+    "ks_propose": ([_vp, _vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp, _vp, _u64, _vp], ctypes.c_int),
+    "ks_refine": ([_vp, _vp, _u32, _u64, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "ks_train_step": ([_vp, _vp, _vp, _u64, _vp, _vp, _u32, _u32, ctypes.c_float, _vp, _vp], ctypes.c_int),
 }
 
 
@@ -209,6 +223,116 @@ def ks_autotune(ctx, samples, desc, num_series: int, params: ks_params, out, str
                            ctypes.byref(ms))
     _check(rc, "ks_autotune")
     return best, float(ms.value)
+
+
+def _nelem(x, size):
+    return 0 if x is None else (x.numel() * x.element_size()) // size
+
+
+def ks_model_create(ctx, seed: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().ks_model_create(ctx, seed, ctypes.byref(h)), "ks_model_create")
+    return h
+
+
+def ks_model_destroy(model) -> None:
+    _check(lib().ks_model_destroy(model), "ks_model_destroy")
+
+
+def ks_model_set_params(model, params) -> None:
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    if a.size != KS_CNN_PARAMS:
+        raise ValueError(f"expected {KS_CNN_PARAMS} parameters, got {a.size}")
+    _check(lib().ks_model_set_params(model, a.ctypes.data), "ks_model_set_params")
+
+
+def ks_model_get_params(model) -> np.ndarray:
+    a = np.zeros(KS_CNN_PARAMS, np.float32)
+    _check(lib().ks_model_get_params(model, a.ctypes.data), "ks_model_get_params")
+    return a
+
+
+def ks_model_grads(model) -> np.ndarray:
+    a = np.zeros(KS_CNN_PARAMS, np.float32)
+    _check(lib().ks_model_grads(model, a.ctypes.data), "ks_model_grads")
+    return a
+
+
+def ks_model_save(model, path) -> None:
+    _check(lib().ks_model_save(model, str(path).encode()), "ks_model_save")
+
+
+def ks_model_load(model, path) -> None:
+    _check(lib().ks_model_load(model, str(path).encode()), "ks_model_load")
+
+
+def ks_features(ctx, samples, desc, num_series: int, max_K: int = 0, features=None, stream=None,
+                num_samples: int | None = None) -> None:
+    """Feature pass; features (optional): float32 device buffer of 9 floats per row at aux_offset."""
+    if num_samples is None:
+        num_samples = samples.numel() * samples.element_size() // 4
+    rc = lib().ks_features(ctx, _addr(samples, 4 * num_samples, "samples"), num_samples,
+                           _addr(desc, 24 * num_series, "desc"), num_series, max_K, _addr(features, None, "features"),
+                           _nelem(features, 36), _stream(stream))
+    _check(rc, "ks_features")
+
+
+def ks_cnn_forward(ctx, model, features, desc, num_series: int, max_K: int, logits, stream=None) -> None:
+    rc = lib().ks_cnn_forward(ctx, model, _addr(features, None, "features"), _nelem(features, 36),
+                              _addr(desc, 24 * num_series, "desc"), num_series, max_K, _addr(logits, None, "logits"),
+                              _nelem(logits, 4), _stream(stream))
+    _check(rc, "ks_cnn_forward")
+
+
+def ks_propose(ctx, model, samples, desc, num_series: int, params: ks_params, proposal, confidence, features=None,
+               stream=None, num_samples: int | None = None) -> None:
+    if num_samples is None:
+        num_samples = samples.numel() * samples.element_size() // 4
+    rc = lib().ks_propose(ctx, model, _addr(samples, 4 * num_samples, "samples"), num_samples,
+                          _addr(desc, 24 * num_series, "desc"), num_series, ctypes.byref(params),
+                          _addr(proposal, 4 * num_series, "proposal"), _addr(confidence, 4 * num_series, "confidence"),
+                          _addr(features, None, "features"), _nelem(features, 36), _stream(stream))
+    _check(rc, "ks_propose")
+
+
+def ks_refine(ctx, desc, num_series: int, num_samples: int, proposal, confidence, params: ks_params, out,
+              stream=None) -> None:
+    rc = lib().ks_refine(ctx, _addr(desc, 24 * num_series, "desc"), num_series, num_samples,
+                         _addr(proposal, 4 * num_series, "proposal"), _addr(confidence, 4 * num_series, "confidence"),
+                         ctypes.byref(params), _addr(out, 48 * num_series, "out"), _stream(stream))
+    _check(rc, "ks_refine")
+
+
+def ks_train_step(ctx, model, features, desc, labels, num_series: int, max_K: int, lr: float, loss=None,
+                  stream=None) -> None:
+    rc = lib().ks_train_step(ctx, model, _addr(features, None, "features"), _nelem(features, 36),
+                             _addr(desc, 24 * num_series, "desc"), _addr(labels, 4 * num_series, "labels"), num_series,
+                             max_K, lr, _addr(loss, 4, "loss"), _stream(stream))
+    _check(rc, "ks_train_step")
+
+
+class Model:
+    """Owns one ks_model (ks_model_create / ks_model_destroy)."""
+
+    def __init__(self, ctx, seed: int = 0):
+        self.handle = ks_model_create(ctx.handle if isinstance(ctx, Context) else ctx, seed)
+
+    def close(self):
+        if self.handle is not None:
+            ks_model_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- convenience

@@ -32,6 +32,7 @@ HIP_FLAGS = [
 
 KS_SOURCES = [
     "csrc/ks_api.hip",
+    "csrc/ks_learn.hip",
 ]
 
 TARGETS = {

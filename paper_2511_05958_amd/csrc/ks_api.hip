@@ -13,55 +13,12 @@
 #include <tuple>
 
 #include "ks.h"
+#include "ks_ctx.hpp"
 #include "ks_persist.hpp"
 
-namespace {
+using namespace ks_host;
 
-constexpr int kNT = 256;
-constexpr int kRB = 4;
-constexpr int kNumKClasses = 6;
-constexpr uint32_t kKClass[kNumKClasses] = {64, 128, 256, 512, 1024, 2048};
-
-int k_class(uint32_t max_K) {
-  for (int i = 0; i < kNumKClasses; ++i)
-    if (max_K <= kKClass[i]) return i;
-  return kNumKClasses - 1;
-}
-
-// Launch configuration chosen per (K class) and batch size by the tuner.
-struct LaunchCfg {
-  int mode = KS_LAUNCH_ORDERED;  // KS_LAUNCH_GRID / _PERSISTENT / _ORDERED
-  uint32_t chunk_bytes = 1u << 20;
-  int graph = 1;                 // planned launches replayed from a hipGraph
-};
-
-struct GraphEntry {
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipGraphNode_t node[3] = {nullptr, nullptr, nullptr};
-  int nodes = 0;
-};
-
-}  // namespace
-
-struct ks_ctx {
-  int device = 0;
-  int num_cus = 0;
-  std::string arch;
-  int occupancy[kNumKClasses] = {0};  // resident workgroups per CU of scan_persistent
-  // workspace
-  uint32_t* hdr = nullptr;
-  ks::Item* items = nullptr;
-  uint64_t* mom_base = nullptr;
-  uint32_t* done = nullptr;
-  uint32_t* smin = nullptr;
-  ks::RowMom* mom = nullptr;
-  uint64_t cap_series = 0, cap_rows = 0;
-  std::map<std::tuple<int, int, uint32_t>, GraphEntry> graphs;  // (mode, K class, grid)
-  std::map<std::tuple<int, uint32_t>, LaunchCfg> tuned;     // (K class, num_series)
-};
-
-namespace {
+namespace ks_host {
 
 thread_local char g_hip_msg[256] = "HIP error";
 
@@ -70,33 +27,9 @@ int hip_fail(hipError_t e, const char* what) {
   return KS_E_HIP;
 }
 
-// Make the context's device current for the duration of a call.
-struct DeviceGuard {
-  int prev = -1;
-  bool changed = false;
-  hipError_t err = hipSuccess;
-  explicit DeviceGuard(int dev) {
-    err = hipGetDevice(&prev);
-    if (err == hipSuccess && prev != dev) {
-      err = hipSetDevice(dev);
-      changed = err == hipSuccess;
-    }
-  }
-  ~DeviceGuard() {
-    if (changed) (void)hipSetDevice(prev);
-  }
-};
+}  // namespace ks_host
 
-int check_params(const ks_params* p) {
-  if (!p) return KS_E_INVALID;
-  if (!(p->alpha > 0.0 && p->alpha < 1.0)) return KS_E_INVALID;
-  if (!(p->c_alpha > 0.0) || !std::isfinite(p->c_alpha)) return KS_E_INVALID;
-  if (p->w < 1 || p->w > 64) return KS_E_INVALID;
-  if (!(p->tau >= 0.0f && p->tau <= 1.0f)) return KS_E_INVALID;
-  if (p->opts & ~(uint32_t)KS_OPT_MASK) return KS_E_INVALID;
-  if (p->max_K != 0 && (p->max_K < 2 || p->max_K > KS_MAX_K)) return KS_E_RANGE;
-  return KS_OK;
-}
+namespace {
 
 void free_workspace(ks_ctx* c) {
   (void)hipFree(c->hdr);
@@ -399,6 +332,7 @@ int ks_ctx_destroy(ks_ctx* ctx) {
       (void)hipGraphDestroy(kv.second.graph);
     }
     free_workspace(ctx);
+    free_learn(ctx->learn);
   }
   delete ctx;
   return KS_OK;

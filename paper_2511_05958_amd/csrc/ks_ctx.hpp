@@ -1,0 +1,136 @@
+// Host-side state shared by the library's translation units: the context,
+// the model, error text and common validation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <tuple>
+
+#include "ks.h"
+
+namespace ks {
+struct Item;
+struct RowMom;
+}  // namespace ks
+
+namespace ks_host {
+
+constexpr int kNT = 256;
+constexpr int kRB = 4;
+constexpr int kNumKClasses = 6;
+constexpr uint32_t kKClass[kNumKClasses] = {64, 128, 256, 512, 1024, 2048};
+
+inline int k_class(uint32_t max_K) {
+  for (int i = 0; i < kNumKClasses; ++i)
+    if (max_K <= kKClass[i]) return i;
+  return kNumKClasses - 1;
+}
+
+// Launch configuration chosen per (K class) and batch size by the tuner.
+struct LaunchCfg {
+  int mode = KS_LAUNCH_ORDERED;  // KS_LAUNCH_GRID / _PERSISTENT / _ORDERED
+  uint32_t chunk_bytes = 1u << 20;
+  int graph = 1;                 // planned launches replayed from a hipGraph
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node[3] = {nullptr, nullptr, nullptr};
+  int nodes = 0;
+};
+
+// Device buffers of the learned path, grown on demand.
+struct LearnBuffers {
+  // proposal pass (rows = num_series * SR)
+  uint64_t* s1 = nullptr;
+  uint64_t* s2lo = nullptr;
+  uint32_t* s2hi = nullptr;
+  uint32_t* smin = nullptr;
+  uint32_t* K = nullptr;
+  float* feat = nullptr;      // [rows][9]
+  uint16_t* x0 = nullptr;     // [rows][16] bf16
+  uint16_t* act[3] = {nullptr, nullptr, nullptr};  // [rows][64] bf16 (a1, a2, a3)
+  float* logits = nullptr;    // [rows]
+  // training
+  uint16_t* dy16 = nullptr;   // [rows][16] bf16: logit gradient
+  float* dy16f = nullptr;
+  uint16_t* dy[2] = {nullptr, nullptr};  // [rows][64] bf16
+  float* dyf[2] = {nullptr, nullptr};
+  float* part = nullptr;      // weight-gradient partials
+  float* grad[4] = {nullptr, nullptr, nullptr, nullptr};  // reduced, per layer
+  uint32_t* nsig = nullptr;
+  uint64_t cap_rows = 0, cap_series = 0, cap_part = 0;
+  // the last proposal / feature pass (ks_refine checks it)
+  const void* stamp_desc = nullptr;
+  uint32_t stamp_series = 0, stamp_SR = 0, stamp_maxK = 0;
+  bool stamp_valid = false;
+};
+
+int hip_fail(hipError_t e, const char* what);
+
+// Make the context's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) {
+      err = hipSetDevice(dev);
+      changed = err == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+inline int check_params(const ks_params* p) {
+  if (!p) return KS_E_INVALID;
+  if (!(p->alpha > 0.0 && p->alpha < 1.0)) return KS_E_INVALID;
+  if (!(p->c_alpha > 0.0) || !std::isfinite(p->c_alpha)) return KS_E_INVALID;
+  if (p->w < 1 || p->w > 64) return KS_E_INVALID;
+  if (!(p->tau >= 0.0f && p->tau <= 1.0f)) return KS_E_INVALID;
+  if (p->opts & ~(uint32_t)KS_OPT_MASK) return KS_E_INVALID;
+  if (p->max_K != 0 && (p->max_K < 2 || p->max_K > KS_MAX_K)) return KS_E_RANGE;
+  return KS_OK;
+}
+
+void free_learn(LearnBuffers& b);
+
+}  // namespace ks_host
+
+struct ks_ctx {
+  int device = 0;
+  int num_cus = 0;
+  std::string arch;
+  int occupancy[ks_host::kNumKClasses] = {0};  // resident workgroups per CU of scan_persistent
+  // scan workspace
+  uint32_t* hdr = nullptr;
+  ks::Item* items = nullptr;
+  uint64_t* mom_base = nullptr;
+  uint32_t* done = nullptr;
+  uint32_t* smin = nullptr;
+  ks::RowMom* mom = nullptr;
+  uint64_t cap_series = 0, cap_rows = 0;
+  std::map<std::tuple<int, int, uint32_t>, ks_host::GraphEntry> graphs;  // (mode, K class, grid)
+  std::map<std::tuple<int, uint32_t>, ks_host::LaunchCfg> tuned;         // (K class, num_series)
+  ks_host::LearnBuffers learn;
+};
+
+struct ks_model {
+  int device = 0;
+  float* theta = nullptr;  // master weights, fp32
+  float* m1 = nullptr;     // Adam moments
+  float* m2 = nullptr;
+  float* grad = nullptr;   // gradient of the last training step
+  uint16_t* wf[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint16_t* wb[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* b[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint64_t step = 0;
+};

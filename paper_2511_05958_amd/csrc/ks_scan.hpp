@@ -397,10 +397,15 @@ __device__ bool sort_keys(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, int bits) {
   return (passes & 1) != 0;
 }
 
-// Phases 4-5 for one series already holding moments in LDS.
+// Phases 4-5 for one series already holding moments in LDS: the walk and the
+// choice cover the candidates c_lo..c_hi (inclusive; 1..K-1 for the full
+// scan); extra_flags are or-ed into the result flags.
 template <int KMAX, int NT, int RB>
 __device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N, uint32_t gmin,
-                              const ks_params& prm, ks_result* __restrict__ out, uint32_t* __restrict__ allU) {
+                              const ks_params& prm, ks_result* __restrict__ out, uint32_t* __restrict__ allU,
+                              uint32_t c_lo = 1, uint32_t c_hi = 0xffffffffu, uint32_t extra_flags = 0) {
+  if (c_hi > K - 1) c_hi = K - 1;
+  if (c_lo < 1) c_lo = 1;
   using S = ScanShape<KMAX, NT, RB>;
   const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
   const int bits = make_keys(sm, K, N, gmin);
@@ -424,7 +429,7 @@ __device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N
   // lattice walk over the candidates c = 1 + w, 1 + w + W, ...
   const uint32_t nch = (K + kWave - 1) / kWave;
   uint32_t bU = 0, bC = 0;
-  for (uint32_t c = 1 + w; c < K; c += S::W) {
+  for (uint32_t c = c_lo + w; c <= c_hi; c += S::W) {
     uint32_t carry = 0, mx = 0;
     for (uint32_t k = 0; k < nch; ++k) {
       const uint32_t p = k * kWave + lane;
@@ -457,12 +462,16 @@ __device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N
         c = sm.bestC[v];
       }
     if (allU) allU[0] = 0;
+    if (c == 0) {  // empty range (not reached by the callers)
+      c = c_lo;
+      U = 0;
+    }
     const uint32_t n = c, m = K - c;
     const double U2 = (double)((uint64_t)U * U);
     const double nmK = (double)((uint64_t)n * m * K);
     const double lambda2 = U2 / nmK;
     const double p = U == 0 ? 1.0 : kolmogorov_q(lambda2);
-    const uint32_t flags = (U2 > prm.c_alpha * nmK) ? KS_SIGNIFICANT : 0u;
+    const uint32_t flags = ((U2 > prm.c_alpha * nmK) ? KS_SIGNIFICANT : 0u) | extra_flags;
     write_result(out, c, n, m, U, (double)U / (double)((uint64_t)n * m), sqrt(lambda2), p, flags);
   }
   __syncthreads();

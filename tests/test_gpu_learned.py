@@ -1,0 +1,204 @@
+"""GPU parity of the learned proposal path through the C ABI.
+
+Bars: features bit-exact (float32); the exact refine bit-exact against the
+oracle's windowed choice given the device's proposal and confidence;
+network logits and training gradients within the tolerance that FP32
+accumulation plus bf16 re-rounding of activations allows (logits 1e-2 of their
+range, gradients 2e-2 of the largest entry, both with a near-1 cosine).
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2511_05958_amd as P
+from oracle import cnn as C
+from paper_2511_05958_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(dev):
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def gen(recipe, num, first=0):
+    b = S.make_batch(recipe, num_series=num, first_series=first)
+    x = S.fill_host(b)
+    d = P.make_desc(b.specs["offset"], b.specs["K"], b.specs["N"])
+    return b, x, d
+
+
+def gpu_features(ctx, x, d, max_K):
+    import torch
+
+    rows = int(d["K"].astype(np.int64).sum())
+    feats = torch.full((rows * 9,), float("nan"), dtype=torch.float32, device="cuda")
+    P.ks_features(ctx.handle, P.to_device(x), P.to_device(d), len(d), max_K, feats)
+    torch.cuda.synchronize()
+    return feats.cpu().numpy().reshape(rows, 9)
+
+
+def series(x, d, t):
+    o, K, N = int(d[t]["offset"]), int(d[t]["K"]), int(d[t]["N"])
+    return x[o:o + K * N].reshape(K, N)
+
+
+@pytest.mark.parametrize("recipe,num", [(1, 1), (2, 6), (3, 30), (5, 2)])
+def test_features_bit_exact(ctx, recipe, num):
+    b, x, d = gen(recipe, num)
+    f = gpu_features(ctx, x, d, int(d["K"].max()))
+    for t in range(num):
+        a = int(d[t]["aux_offset"])
+        ref = O.features(series(x, d, t))
+        assert np.array_equal(f[a:a + len(ref)], ref), t
+
+
+def test_features_edge_cases(ctx):
+    rng = np.random.default_rng(3)
+    ss = [np.full((5, 1), 7, np.uint32), np.full((3, 40), 9, np.uint32),
+          rng.integers(0, 2**32 - 1, (4, 4096), dtype=np.uint64).astype(np.uint32),
+          rng.integers(100, 104, (2, 33), dtype=np.uint32), np.array([[0, 1], [5, 5]], np.uint32)]
+    parts, offs, off = [], [], 0
+    for r in ss:
+        offs.append(off)
+        parts.append(r.ravel())
+        off += r.size
+    x = np.concatenate(parts)
+    d = P.make_desc(offs, [r.shape[0] for r in ss], [r.shape[1] for r in ss])
+    f = gpu_features(ctx, x, d, 64)
+    for t, r in enumerate(ss):
+        a = int(d[t]["aux_offset"])
+        assert np.array_equal(f[a:a + r.shape[0]], O.features(r)), t
+
+
+def test_forward_matches_oracle(ctx):
+    import torch
+
+    b, x, d = gen(2, 6, first=10)
+    feats = np.concatenate([O.features(series(x, d, t)) for t in range(6)])
+    with P.Model(ctx, seed=11) as m:
+        theta = P.ks_model_get_params(m.handle).astype(np.float64)
+        lg = torch.zeros(len(feats), dtype=torch.float32, device="cuda")
+        P.ks_cnn_forward(ctx.handle, m.handle, P.to_device(feats.ravel()).view(torch.float32), P.to_device(d), 6, 256, lg)
+        torch.cuda.synchronize()
+        z = lg.cpu().numpy()
+    for t in range(6):
+        a, K = int(d[t]["aux_offset"]), int(d[t]["K"])
+        zo, _ = C.forward(feats[a:a + K], theta, round_bf16=True)
+        zg = z[a:a + K].astype(np.float64)
+        assert np.max(np.abs(zg - zo)) <= 1e-2 * (np.ptp(zo) + 1e-6), t
+        cos = zg @ zo / (np.linalg.norm(zg) * np.linalg.norm(zo))
+        assert cos > 0.9999, t
+
+
+def test_propose_and_refine_exact(ctx):
+    import torch
+
+    b, x, d = gen(2, 24, first=100)
+    n = len(d)
+    s_d, d_d = P.to_device(x), P.to_device(d)
+    prm = P.ks_params_init(0.05)
+    prm.max_K = 256
+    prop = torch.zeros(n, dtype=torch.int32, device="cuda")
+    conf = torch.zeros(n, dtype=torch.float32, device="cuda")
+    out = P.empty_results(n)
+    oracle_all = [O.scan_series(series(x, d, t), want_allU=True) for t in range(n)]
+    with P.Model(ctx, seed=5) as m:
+        P.ks_propose(ctx.handle, m.handle, s_d, d_d, n, prm, prop, conf)
+        torch.cuda.synchronize()
+        pg, cg = prop.cpu().numpy(), conf.cpu().numpy()
+        # the proposal is the argmax of the network's logits on the same features
+        feats = np.concatenate([O.features(series(x, d, t)) for t in range(n)])
+        lg = torch.zeros(len(feats), dtype=torch.float32, device="cuda")
+        P.ks_cnn_forward(ctx.handle, m.handle, P.to_device(feats.ravel()).view(torch.float32), d_d, n, 256, lg)
+        torch.cuda.synchronize()
+        z = lg.cpu().numpy()
+        for t in range(n):
+            a, K = int(d[t]["aux_offset"]), int(d[t]["K"])
+            c, cf = C.propose(z[a:a + K], prm.w)
+            assert pg[t] == c and abs(cg[t] - cf) <= 1e-5, t
+        # ks_cnn_forward reused the slot buffers: run the proposal pass again before refining
+        P.ks_propose(ctx.handle, m.handle, s_d, d_d, n, prm, prop, conf)
+        for w, tau in [(8, 0.0), (8, 0.5), (3, 0.9), (64, 0.2), (1, 1.0)]:
+            prm.w, prm.tau = w, tau
+            P.ks_refine(ctx.handle, d_d, n, len(x), prop, conf, prm, out)
+            torch.cuda.synchronize()
+            g = P.results_to_numpy(out)
+            for t in range(n):
+                res, U = oracle_all[t]
+                r = O.refine(U, int(d[t]["K"]), int(pg[t]), float(cg[t]), w, tau)
+                assert (g[t]["cp"], g[t]["U"], g[t]["n"], g[t]["m"]) == (r["cp"], r["U"], r["n"], r["m"]), (w, tau, t)
+                assert g[t]["D"] == r["D"] and g[t]["lambda"] == r["lambda"]
+                assert g[t]["p"] == r["p"] or abs(g[t]["p"] - r["p"]) <= 1e-12 * r["p"]
+                assert bool(g[t]["flags"] & P.KS_SIGNIFICANT) == bool(r["significant"])
+                want = P.KS_REFINED if r["refined"] else P.KS_FALLBACK
+                assert g[t]["flags"] & (P.KS_REFINED | P.KS_FALLBACK) == want
+                if not r["refined"]:
+                    assert (g[t]["cp"], g[t]["U"]) == (res["cp"], res["U"])
+        # NaN confidence falls back to the full scan
+        prm.w, prm.tau = 8, 0.5
+        nanc = torch.full((n,), float("nan"), dtype=torch.float32, device="cuda")
+        P.ks_refine(ctx.handle, d_d, n, len(x), prop, nanc, prm, out)
+        torch.cuda.synchronize()
+        g = P.results_to_numpy(out)
+        assert (g["flags"] & P.KS_FALLBACK).all()
+        assert np.array_equal(g["cp"], np.array([r[0]["cp"] for r in oracle_all]))
+        # call-order check
+        with pytest.raises(P.KsError) as e:
+            P.ks_refine(ctx.handle, d_d, n - 1, len(x), prop, conf, prm, out)
+        assert e.value.code == P.KS_E_STATE
+
+
+def test_train_step_gradient_loss_and_adam(ctx):
+    import torch
+
+    b, x, d = gen(2, 8, first=200)
+    n = len(d)
+    feats = np.concatenate([O.features(series(x, d, t)) for t in range(n)])
+    labels = []
+    for t in range(n):
+        r = O.scan_series(series(x, d, t))
+        labels.append(int(r["cp"]) if r["significant"] else -1)
+    assert sum(c >= 1 for c in labels) >= 3
+    with P.Model(ctx, seed=21) as m:
+        theta = P.ks_model_get_params(m.handle).astype(np.float64)
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        lab = torch.tensor(labels, dtype=torch.int32, device="cuda")
+        lr = 1e-3
+        P.ks_train_step(ctx.handle, m.handle, P.to_device(feats.ravel()).view(torch.float32), P.to_device(d), lab, n, 256,
+                        lr, loss)
+        torch.cuda.synchronize()
+        g = P.ks_model_grads(m.handle).astype(np.float64)
+        theta1 = P.ks_model_get_params(m.handle).astype(np.float64)
+    fl = [feats[int(d[t]["aux_offset"]):int(d[t]["aux_offset"]) + int(d[t]["K"])] for t in range(n)]
+    lo, go = C.batch_loss_grad(fl, labels, theta, round_bf16=True)
+    assert abs(float(loss.cpu()[0]) - lo) <= 1e-3 * abs(lo)
+    assert np.max(np.abs(g - go)) <= 2e-2 * np.max(np.abs(go))
+    assert g @ go / (np.linalg.norm(g) * np.linalg.norm(go)) > 0.9999
+    th, _, _ = C.adam_step(theta, np.zeros_like(theta), np.zeros_like(theta), g, 1, lr)
+    assert np.max(np.abs(theta1 - th)) <= 1e-5 * lr + 1e-7 * np.max(np.abs(theta))
+
+
+def test_checkpoint_roundtrip_and_corruption(ctx, tmp_path):
+    with P.Model(ctx, seed=3) as a, P.Model(ctx, seed=4) as bm:
+        pa = P.ks_model_get_params(a.handle)
+        path = tmp_path / "m.ckpt"
+        P.ks_model_save(a.handle, path)
+        P.ks_model_load(bm.handle, path)
+        assert np.array_equal(P.ks_model_get_params(bm.handle), pa)
+        raw = bytearray(path.read_bytes())
+        raw[100] ^= 0x40
+        bad = tmp_path / "bad.ckpt"
+        bad.write_bytes(bytes(raw))
+        with pytest.raises(P.KsError) as e:
+            P.ks_model_load(bm.handle, bad)
+        assert e.value.code == P.KS_E_MODEL
+        nanp = pa.copy()
+        nanp[7] = np.nan
+        with pytest.raises(P.KsError) as e:
+            P.ks_model_set_params(bm.handle, nanp)
+        assert e.value.code == P.KS_E_MODEL
