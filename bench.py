@@ -24,6 +24,7 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_05958_amd", "models")
 
 WORKLOADS = {
     "c1": (1, None, "plain exact scan, 1 series x K=64 x N=256 (one 120->320 cycle change)"),
@@ -72,6 +73,63 @@ def cpu_baseline(batch, samples_dev, threads: int, target_s: float = 10.0, max_b
     }
 
 
+def learned_leg(args, ctx, batch, samples, desc, out_plain, prm, stream, res_plain, plain_value) -> dict:
+    """Propose + exact refine on the same batch, timed like the plain step; agreement with the plain scan."""
+    import numpy as np
+    import torch
+
+    import paper_2511_05958_amd as P
+
+    rep_path = os.path.splitext(args.model)[0] + ".json"
+    with open(rep_path) as f:
+        rep = json.load(f)
+    n = batch.num_series
+    lp = P.ks_params_init(prm.alpha)
+    lp.max_K = prm.max_K
+    lp.w = 8
+    lp.tau = float(rep["tau"])
+    model = P.Model(ctx, seed=0)
+    P.ks_model_load(model.handle, args.model)
+    prop = torch.empty(n, dtype=torch.int32, device="cuda")
+    conf = torch.empty(n, dtype=torch.float32, device="cuda")
+    out = P.empty_results(n)
+
+    def step():
+        P.ks_propose(ctx.handle, model.handle, samples, desc, n, lp, prop, conf, stream=stream)
+        P.ks_refine(ctx.handle, desc, n, batch.total_elems, prop, conf, lp, out, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    r = P.results_to_numpy(out)
+    agree = (r["cp"] == res_plain["cp"]) & (r["U"] == res_plain["U"])
+    value = n / (wall_ms / 1e3)
+    model.close()
+    return {
+        "value": value,
+        "unit": "series/s",
+        "ms_per_step": wall_ms,
+        "step_ms_events": ev_ms,
+        "vs_plain": value / plain_value,
+        "agreement": float(agree.mean()),
+        "fallback_rate": float(np.mean((r["flags"] & P.KS_FALLBACK) != 0)),
+        "w": lp.w,
+        "tau": lp.tau,
+        "hbm_GBps_whole_step": (batch.sample_bytes + 48 * n) / (ev_ms / 1e3) / 1e9,
+        "model": os.path.basename(args.model),
+    }
+
+
 def copy_calibration(args) -> int:
     import torch
 
@@ -106,6 +164,9 @@ def main() -> int:
                          "one workgroup per series, largest-first ordered grid, persistent queue (hipGraph), "
                          "persistent queue with direct launches")
     ap.add_argument("--chunk", type=int, default=1 << 20, help="split size of the persistent plan (bytes)")
+    ap.add_argument("--model", default=os.path.join(MODEL_DIR, "proposal_r4.ckpt"),
+                    help="trained proposal network; its .json report holds tau (learned mode is skipped if absent)")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -202,6 +263,8 @@ def main() -> int:
             "kernel_ms": avg_kern_s * 1e3,
         },
     }
+    if not args.no_learned and os.path.exists(args.model) and batch.specs["N"].max() <= P.KS_FEATURE_MAX_N:
+        line["learned"] = learned_leg(args, ctx, batch, samples, desc, out, prm, stream, res, n / (ms_per_step / 1e3))
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))
         line["cpu_baseline"] = cpu_baseline(batch, samples, threads)

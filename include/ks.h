@@ -218,17 +218,19 @@ int ks_autotune(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, cons
  * choice then runs only within +-w rows of the proposal (ks_refine), or over
  * all candidates when the proposal's confidence is below tau.
  *
- * Network: conv(9->64) ReLU, conv(64->64) ReLU, conv(64->64) ReLU,
+ * Network: conv(11->64) ReLU, conv(64->64) ReLU, conv(64->64) ReLU,
  * conv(64->1), kernel 5, zero padding 2, bias; one logit per row; bf16
- * operands on the matrix cores with fp32 accumulation. Parameters
- * (KS_CNN_PARAMS fp32 values, in this order): W0[64][9][5] b0[64]
- * W1[64][64][5] b1[64] W2[64][64][5] b2[64] W3[1][64][5] b3[1].
+ * operands on the matrix cores with fp32 accumulation. Input channels of row
+ * t: the nine features, t / (K-1) and 4 t (K - t) / K^2 (double, rounded to
+ * float; the K-S choice favours central splits). Parameters (KS_CNN_PARAMS
+ * fp32 values, in this order): W0[64][11][5] b0[64] W1[64][64][5] b1[64]
+ * W2[64][64][5] b2[64] W3[1][64][5] b3[1].
  * Features: for row i the nine deciles x_(floor(k (N-1)/10)), k = 1..9, of
  * the row's samples, f = (double)(x - m) / max(m, 1) rounded to float, m the
  * series minimum; layout float[row][9] with series s at rows aux_offset.. .
  * ------------------------------------------------------------------------ */
 
-#define KS_CNN_PARAMS 44353u
+#define KS_CNN_PARAMS 44993u
 #define KS_FEATURE_MAX_N 4096u /* largest N the feature pass accepts */
 
 typedef struct ks_model ks_model;

@@ -3,9 +3,11 @@
 The paper has no learned stage: the network shortlists candidate change
 points, which the paper mentions as a way to cut the K-S evaluation
 (workflow step 4, last paragraph) and omits because its data are small. It is
-a 1-D CNN over the per-row decile features:
+a 1-D CNN over the per-row decile features plus two position channels
+(t / (K-1) and 4 t (K - t) / K^2, computed in double and rounded to float:
+the K-S choice favours central splits, lambda^2 = D^2 c (K - c) / K):
 
-    conv(9 -> 64) ReLU, conv(64 -> 64) ReLU, conv(64 -> 64) ReLU, conv(64 -> 1)
+    conv(11 -> 64) ReLU, conv(64 -> 64) ReLU, conv(64 -> 64) ReLU, conv(64 -> 1)
 
 every conv with kernel 5, zero padding 2, bias; one logit per row t. The
 proposal is the softmax over rows t = 1..K-1 (the candidate change points).
@@ -17,7 +19,7 @@ device. Activations between layers are FP32 before that rounding. With
 ``round_bf16=False`` every rounding is skipped (the plain FP64 network used by
 the finite-difference pins).
 
-Parameter vector layout (float32, 44353 values): W0[64][9][5], b0[64],
+Parameter vector layout (float32, 44993 values): W0[64][11][5], b0[64],
 W1[64][64][5], b1[64], W2[64][64][5], b2[64], W3[1][64][5], b3[1].
 """
 
@@ -27,7 +29,7 @@ import numpy as np
 
 KW = 5
 PAD = 2
-LAYERS = [(9, 64), (64, 64), (64, 64), (64, 1)]
+LAYERS = [(11, 64), (64, 64), (64, 64), (64, 1)]
 
 
 def param_shapes():
@@ -39,7 +41,17 @@ def param_shapes():
 
 
 NUM_PARAMS = int(sum(np.prod(s) for s in param_shapes()))
-assert NUM_PARAMS == 44353
+assert NUM_PARAMS == 44993
+
+
+def network_input(feat):
+    """[11][K]: the nine feature columns, then t / (K-1) and 4 t (K - t) / K^2 (float)."""
+    feat = np.asarray(feat, np.float64)
+    K = feat.shape[0]
+    t = np.arange(K, dtype=np.float64)
+    p1 = (t / max(K - 1, 1)).astype(np.float32).astype(np.float64)
+    p2 = (4.0 * t * (K - t) / (float(K) * float(K))).astype(np.float32).astype(np.float64)
+    return np.vstack([feat.T, p1[None], p2[None]])
 
 
 def unpack(theta):
@@ -112,7 +124,7 @@ def forward(feat, theta, round_bf16=True):
     """feat [K][9] -> (logits [K], cache). Logits are exact sums of rounded operands."""
     P = unpack(theta)
     rnd = bf16 if round_bf16 else (lambda v: np.asarray(v, np.float64))
-    a = np.asarray(feat, np.float64).T  # [9][K]
+    a = network_input(feat)  # [11][K]
     cache = {"x": [], "y": []}
     for l in range(4):
         x = rnd(a)

@@ -18,7 +18,7 @@ _LIB_PATH = Path(__file__).resolve().parent / "libks.so"
 KS_VERSION = 10000
 KS_MAX_K = 2048
 KS_MAX_N = 1 << 24
-KS_CNN_PARAMS = 44353
+KS_CNN_PARAMS = 44993
 KS_FEATURE_MAX_N = 4096
 
 KS_OK = 0

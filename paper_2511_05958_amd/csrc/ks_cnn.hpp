@@ -229,21 +229,33 @@ __global__ __launch_bounds__(NTC) void reduce_parts_kernel(const float* __restri
 
 // ---------------------------------------------------------------- parameters
 //
-// Master vector (fp32, 44353): W0[64][9][5] b0[64] W1[64][64][5] b1[64]
-// W2[64][64][5] b2[64] W3[1][64][5] b3[1].
+// Master vector (fp32, 44993): W0[64][11][5] b0[64] W1[64][64][5] b1[64]
+// W2[64][64][5] b2[64] W3[1][64][5] b3[1]. Input channels of layer 0: the nine
+// decile features, then t / (K-1) and 4 t (K - t) / K^2.
 struct Layer {
   int cin, cout, cin_pad, cout_pad;
   uint32_t w_off, b_off;
 };
 __device__ __host__ inline Layer layer_info(int l) {
   switch (l) {
-    case 0: return Layer{9, 64, 16, 64, 0u, 2880u};
-    case 1: return Layer{64, 64, 64, 64, 2944u, 23424u};
-    case 2: return Layer{64, 64, 64, 64, 23488u, 43968u};
-    default: return Layer{64, 1, 64, 16, 44032u, 44352u};
+    case 0: return Layer{11, 64, 16, 64, 0u, 3520u};
+    case 1: return Layer{64, 64, 64, 64, 3584u, 24064u};
+    case 2: return Layer{64, 64, 64, 64, 24128u, 44608u};
+    default: return Layer{64, 1, 64, 16, 44672u, 44992u};
   }
 }
-constexpr uint32_t kNumParams = 44353;
+constexpr uint32_t kNumParams = 44993;
+
+// Position channels of row t of a K-row series (double, rounded to float).
+__device__ __forceinline__ float pos_frac(uint32_t t, uint32_t K) {
+  return (float)((double)t / (double)(K > 1 ? K - 1 : 1));
+}
+__device__ __forceinline__ float pos_centre(uint32_t t, uint32_t K) {
+  return (float)(4.0 * (double)t * (double)(K - t) / ((double)K * (double)K));
+}
+
+// Entries of all shadow copies (forward weights and biases of every layer).
+constexpr uint32_t kShadowEntries = (64 * 5 * 16 + 64) + 2 * (64 * 5 * 64 + 64) + (16 * 5 * 64 + 16);
 
 // Device copies used by the kernels.
 struct Shadow {
@@ -428,7 +440,14 @@ __global__ __launch_bounds__(NTC) void pack_features_kernel(const float* __restr
   for (uint32_t q = threadIdx.x; q < SR * 16; q += NTC) {
     const uint32_t r = q / 16, k = q - r * 16;
     uint16_t b = 0;
-    if (k < 9 && r >= 2 && r - 2 < K) b = f2bf(feat[(d.aux_offset + r - 2) * 9 + k]);
+    if (r >= 2 && r - 2 < K) {
+      if (k < 9)
+        b = f2bf(feat[(d.aux_offset + r - 2) * 9 + k]);
+      else if (k == 9)
+        b = f2bf(pos_frac(r - 2, K));
+      else if (k == 10)
+        b = f2bf(pos_centre(r - 2, K));
+    }
     x0[((uint64_t)s * SR + r) * 16 + k] = b;
   }
   if (threadIdx.x == 0) Ks[s] = K;

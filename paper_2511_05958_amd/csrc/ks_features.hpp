@@ -7,6 +7,7 @@
 // rounded to float (project-defined inputs of the network).
 #pragma once
 
+#include "ks_cnn.hpp"
 #include "ks_scan.hpp"
 
 namespace ks {
@@ -207,15 +208,20 @@ __global__ __launch_bounds__(NT) void features_kernel(const uint32_t* __restrict
     if (to_user) feat_out[(d.aux_offset + i) * 9 + k] = f;
   }
   __syncthreads();
-  // network input: bf16 of the features, 16 channels per row (9..15 zero); the
-  // slot's rows outside [2, 2 + K) stay zero (they are the conv's zero padding)
+  // network input: bf16 of the features and the two position channels, 16
+  // channels per row (11..15 zero); the slot's rows outside [2, 2 + K) stay
+  // zero (they are the conv's zero padding)
   const uint64_t base = (uint64_t)s * SR;
   for (uint32_t q = tid; q < SR * 16; q += NT) {
     const uint32_t r = q / 16, k = q - r * 16;
     uint16_t b = 0;
-    if (k < 9 && r >= 2 && r < K + 2) {
-      const uint32_t u = __float_as_uint(feat_ws[(base + r) * 9 + k]);
-      b = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    if (r >= 2 && r < K + 2) {
+      if (k < 9)
+        b = cnn::f2bf(feat_ws[(base + r) * 9 + k]);
+      else if (k == 9)
+        b = cnn::f2bf(cnn::pos_frac(r - 2, K));
+      else if (k == 10)
+        b = cnn::f2bf(cnn::pos_centre(r - 2, K));
     }
     x0[(base + r) * 16 + k] = b;
   }

@@ -114,7 +114,7 @@ hipError_t shadow(ks_model* m, hipStream_t st) {
     sh.wb[l] = m->wb[l];
     sh.b[l] = m->b[l];
   }
-  hipLaunchKernelGGL(C::shadow_kernel, dim3((51408 + C::NTC - 1) / C::NTC), dim3(C::NTC), 0, st, m->theta, sh);
+  hipLaunchKernelGGL(C::shadow_kernel, dim3((C::kShadowEntries + C::NTC - 1) / C::NTC), dim3(C::NTC), 0, st, m->theta, sh);
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ def rand_theta(seed, scale=0.2):
 
 def torch_net(theta, feat, round_bf16):
     P = [torch.tensor(p, dtype=torch.float64, requires_grad=True) for p in C.unpack(theta)]
-    a = torch.tensor(np.asarray(feat, np.float64).T[None], dtype=torch.float64)
+    a = torch.tensor(C.network_input(feat)[None], dtype=torch.float64)
 
     def rnd(t):
         return t.float().bfloat16().double() if round_bf16 else t
@@ -130,6 +130,12 @@ def test_adam_matches_torch():
         opt.step()
         th, m, v = C.adam_step(th, m, v, g, step, 1e-3)
     assert np.max(np.abs(th - p.detach().numpy())) < 1e-14
+
+
+def test_position_channels():
+    x = C.network_input(np.zeros((5, 9), np.float32))
+    assert x.shape == (11, 5)
+    assert np.allclose(x[9], [0, 0.25, 0.5, 0.75, 1.0]) and np.allclose(x[10], [0, 0.64, 0.96, 0.96, 0.64])
 
 
 def test_propose_mass():
