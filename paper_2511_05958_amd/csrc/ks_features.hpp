@@ -1,8 +1,8 @@
 // Learned-proposal stage 1: one read of every sample gives, per row,
 //   - the moments (sum r, sum r^2) that the exact refine turns into eq. 2 keys,
-//   - the nine deciles x_(floor(k (N-1) / 10)), k = 1..9, from an LDS radix
-//     sort of the row's uint32 cycle counts (keys r - row minimum, as many
-//     RB-bit passes as the row's range needs),
+//   - the nine deciles x_(floor(k (N-1) / 10)), k = 1..9, by a wave-level
+//     radix select over the row's uint32 cycle counts (keys r - row minimum,
+//     as many digit levels as the row's range needs),
 // and per series the minimum m, then features f = (double)(x - m) / max(m, 1)
 // rounded to float (project-defined inputs of the network).
 #pragma once
@@ -21,182 +21,245 @@ struct LearnWs {
   uint32_t* K;      // [num_series]: K when the series was valid, 0 otherwise
 };
 
-template <int NMAX, int NT, int RB>
-struct RowSortShape {
-  static constexpr int W = NT / kWave;
-  static constexpr int E = (NMAX + NT - 1) / NT;  // samples per thread
-  static constexpr int D = 1 << RB;
-  static constexpr int H = D * E * W;
+// ------------------------------------------------------------------ deciles
+// Nine order statistics of one row, found by one wave with no block barrier:
+// an MSD radix select over the keys r - row minimum. Level 0 histograms the
+// top kSelW0 bits of every key; each later level histograms the next kSelW
+// bits of only the keys that share a target's prefix so far. Those keys form
+// at most nine groups (one per distinct prefix among the targets), numbered in
+// target order. After each level every key is rewritten in place as
+// (group << s) | (its s low bits), s the bits still unresolved, with group
+// kSelNone for keys outside every group, so the next level's bin is the key
+// shifted right by the next s. Histograms are LDS counters per (group, digit)
+// bin; the bins of group kSelNone are counted but never read.
+
+constexpr uint32_t kSelW0 = 8;     // bits of the level-0 digit
+constexpr uint32_t kSelW = 7;      // bits of every later digit
+constexpr uint32_t kSelNone = 9;   // group of keys outside every target's prefix
+
+struct SelLds {
+  uint32_t hist[(kSelNone + 1) << kSelW];  // bin counts, then exclusive prefixes
+  uint8_t tab[(kSelNone + 1) << kSelW];    // bin -> group at the next level
 };
 
-template <int NMAX, int NT, int RB>
-struct FeatSmem {
-  using S = RowSortShape<NMAX, NT, RB>;
-  uint32_t key[2][NMAX];
-  uint16_t hist[S::H];
-  uint32_t red[S::W * 8];
-  uint32_t dec[9];
-};
-
-// Block-wide stable LSD radix sort of n <= NMAX uint32 keys held as E per
-// thread (element e of thread t is item e*NT + t). The sorted keys end in
-// sm.key[result].
-template <int NMAX, int NT, int RB>
-__device__ int block_sort_u32(FeatSmem<NMAX, NT, RB>& sm, uint32_t (&v)[RowSortShape<NMAX, NT, RB>::E], uint32_t n,
-                              int bits) {
-  using S = RowSortShape<NMAX, NT, RB>;
-  const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-  constexpr int C = (S::H + NT - 1) / NT;
-  const int passes = (bits + RB - 1) / RB;
-  int cur = 0;
-#pragma unroll
-  for (int e = 0; e < S::E; ++e) {
-    const uint32_t item = e * NT + tid;
-    if (item < n) sm.key[0][item] = v[e];
-  }
-  __syncthreads();
-  for (int p = 0; p < passes; ++p) {
-    const int shift = p * RB;
-    for (int h = tid; h < S::H; h += NT) sm.hist[h] = 0;
-    __syncthreads();
-    uint32_t dg[S::E], rk[S::E];
-#pragma unroll
-    for (int e = 0; e < S::E; ++e) {
-      const uint32_t item = e * NT + tid;
-      const bool valid = item < n;
-      const uint32_t d = valid ? (sm.key[cur][item] >> shift) & (S::D - 1) : 0u;
-      uint64_t peers = ballot(valid);
-#pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = ballot(bit);
-        peers &= bit ? m : ~m;
-      }
-      dg[e] = d;
-      rk[e] = mbcnt(peers);
-      if (valid && rk[e] == 0) sm.hist[(d * S::E + e) * S::W + w] = (uint16_t)__popcll(peers);
-    }
-    __syncthreads();
-    uint32_t local = 0;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int h = tid * C + c;
-      if (h < S::H) local += sm.hist[h];
-    }
-    const uint32_t incl = wave_incl_scan(local);
-    if (lane == kWave - 1) sm.red[w] = incl;
-    __syncthreads();
-    uint32_t run = incl - local;
-    for (uint32_t u = 0; u < w; ++u) run += sm.red[u];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int h = tid * C + c;
-      if (h < S::H) {
-        const uint32_t x = sm.hist[h];
-        sm.hist[h] = (uint16_t)run;
-        run += x;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < S::E; ++e) {
-      const uint32_t item = e * NT + tid;
-      if (item < n) sm.key[cur ^ 1][sm.hist[(dg[e] * S::E + e) * S::W + w] + rk[e]] = sm.key[cur][item];
-    }
-    __syncthreads();
-    cur ^= 1;
-  }
-  return cur;
+// LDS accesses of one wave are performed in order; this keeps the compiler
+// from moving them across the point where lanes exchange data through LDS.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Features of one series per workgroup. Writes: the caller's FP32 features
+// k[]: this lane's keys (values - row minimum; slots without a sample hold
+// 2^b - 1, which sorts at or after the row maximum), b >= 1 the bit length of
+// the row's range; the keys are consumed. Lane j < 9 returns the key of rank
+// floor((j + 1)(N - 1) / 10).
+template <int V>
+__device__ __forceinline__ uint32_t wave_deciles(SelLds& L, uint32_t (&k)[V], uint32_t b, uint32_t N,
+                                                 uint32_t lane) {
+  const bool tl = lane < 9;
+  uint32_t R = tl ? (uint32_t)(((uint64_t)(lane + 1) * (N - 1)) / 10u) : 0u;  // rank within the group
+  uint32_t tg = 0, key = 0, G = 1, sprev = b, wmax = kSelW0;
+#pragma unroll 1
+  for (;;) {
+    const uint32_t w = min(sprev, wmax);
+    const uint32_t s = sprev - w;
+    const uint32_t T = G << w;  // live bins: groups 0..G-1
+    for (uint32_t q = lane; q < T; q += kWave) L.hist[q] = 0u;
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      atomicAdd(&L.hist[k[e] >> s], 1u);
+      if (e % 8 == 7) __builtin_amdgcn_sched_barrier(0);  // bounds the addresses in flight
+    }
+    wave_lds_sync();
+    // exclusive prefix over the live bins, lane-contiguous chunks
+    const uint32_t C = (T + kWave - 1) / kWave, b0 = lane * C;
+    uint32_t sum = 0;
+    for (uint32_t c = 0; c < C; ++c)
+      if (b0 + c < T) sum += L.hist[b0 + c];
+    uint32_t run = wave_incl_scan(sum) - sum;
+    for (uint32_t c = 0; c < C; ++c)
+      if (b0 + c < T) {
+        const uint32_t h = L.hist[b0 + c];
+        L.hist[b0 + c] = run;
+        run += h;
+      }
+    wave_lds_sync();
+    // each target: the last bin of its group whose prefix is <= its rank
+    uint32_t x = 0;
+    if (tl) {
+      const uint32_t x0 = tg << w;
+      const uint32_t Rg = L.hist[x0] + R;
+      x = x0;
+      for (uint32_t bit = w; bit-- > 0;) {
+        const uint32_t y = x + (1u << bit);
+        if (L.hist[y] <= Rg) x = y;
+      }
+      R = Rg - L.hist[x];
+      key = (key << w) | (x - x0);
+    }
+    if (s == 0) break;
+    // groups of the next level: the targets' distinct bins, in target order
+    const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    const bool fresh = tl && (lane == 0 || x != prev);
+    const uint64_t m = ballot(fresh);
+    const uint32_t id = mbcnt(m) - (fresh ? 0u : 1u);
+    const uint32_t words = ((wmax == kSelW0 ? 1u : kSelNone + 1) << w) / 4u;  // bins incl. group kSelNone
+    uint32_t* tw = reinterpret_cast<uint32_t*>(L.tab);
+    for (uint32_t q = lane; q < words; q += kWave) tw[q] = kSelNone * 0x01010101u;
+    wave_lds_sync();
+    if (tl) L.tab[x] = (uint8_t)id;
+    wave_lds_sync();
+    // a fresh copy of s, so that the compiler recomputes each bin here rather
+    // than keeping all of them live from the histogram loop
+    uint32_t s2 = s;
+    asm volatile("" : "+v"(s2));
+    const uint32_t low = (1u << s) - 1u;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      k[e] = ((uint32_t)L.tab[k[e] >> s2] << s) | (k[e] & low);
+      if (e % 8 == 7) __builtin_amdgcn_sched_barrier(0);  // bounds the lookups in flight
+    }
+    wave_lds_sync();
+    tg = id;
+    G = (uint32_t)__popcll(m);
+    sprev = s;
+    wmax = kSelW;
+  }
+  return key;
+}
+
+// Batches of one row (NB of them; batches past the row's last are empty).
+template <int NB>
+__device__ __forceinline__ void load_row(Batch (&B)[NB], const uint32_t* __restrict__ samples, uint64_t e0,
+                                         uint32_t N, uint32_t lane) {
+  const RowGeo g = row_geo(samples, e0, N);
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    if ((uint32_t)u < g.nb) {
+      load_batch(B[u], samples, g, u, lane);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) B[u].q[q] = u32x4{0u, 0u, 0u, 0u};
+      B[u].x = 0;
+      B[u].m = 0;
+    }
+  }
+}
+
+// One row: moments (sum r, sum r^2), minimum and the nine deciles (lanes 0..8).
+template <int NB>
+__device__ __forceinline__ uint32_t feature_row(SelLds& L, const Batch (&B)[NB], uint32_t N, uint32_t lane,
+                                                uint64_t& s1, uint64_t& s2, uint32_t& s2h, uint32_t& dec) {
+  uint32_t mn = 0xffffffffu, mx = 0u;
+  s1 = 0;
+  s2 = 0;
+  s2h = 0;
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (B[u].m & (1u << q)) {
+        acc_quad(B[u].q[q], mn, s1, s2, s2h);
+        mx = max(mx, max(max(B[u].q[q].x, B[u].q[q].y), max(B[u].q[q].z, B[u].q[q].w)));
+      }
+    if (B[u].m & 16u) {
+      acc_sample(B[u].x, mn, s1, s2, s2h);
+      mx = max(mx, B[u].x);
+    }
+  }
+  wave_total_64_96(s1, s2, s2h);
+  const uint32_t rmin = wave_min_u32(mn), rmax = wave_max_u32(mx);
+  const uint32_t range = rmax - rmin;
+  const uint32_t b = range ? 32u - __clz(range) : 0u;
+  if (b == 0) {
+    dec = rmin;
+    return rmin;
+  }
+  const uint32_t kmax = 0xffffffffu >> (32u - b);
+  uint32_t k[17 * NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool v = (B[u].m >> q) & 1u;
+      k[u * 17 + q * 4 + 0] = v ? B[u].q[q].x - rmin : kmax;
+      k[u * 17 + q * 4 + 1] = v ? B[u].q[q].y - rmin : kmax;
+      k[u * 17 + q * 4 + 2] = v ? B[u].q[q].z - rmin : kmax;
+      k[u * 17 + q * 4 + 3] = v ? B[u].q[q].w - rmin : kmax;
+    }
+    k[u * 17 + 16] = (B[u].m & 16u) ? B[u].x - rmin : kmax;
+  }
+  dec = wave_deciles<17 * NB>(L, k, b, N, lane) + rmin;
+  return rmin;
+}
+
+// Samples per row handled by the NB-batch feature kernel: a row of N samples
+// needs ceil(floor(N / 4) / 256) batches at most.
+__host__ __device__ constexpr uint32_t feat_batches(uint32_t N) {
+  return (N / 4 + 4u * kWave - 1) / (4u * kWave) <= 1 ? 1u : ((N / 4 + 4u * kWave - 1) / (4u * kWave) <= 2 ? 2u : 4u);
+}
+
+// Features of one series per workgroup (series whose rows need NB batches;
+// the NB = 1 launch also clears the slots of malformed series). One wave per
+// row, rows w, w + 4, ... for wave w. Writes: the caller's FP32 features
 // (nullable, rows at aux_offset), the network input rows (bf16, 16 channels,
-// 9 used) at row slot s * SR + 2 + i, and the refine workspace.
-template <int NMAX, int NT, int RB>
+// 11 used) at row slot s * SR + 2 + i, and the refine workspace.
+template <int NB, int NT>
 __global__ __launch_bounds__(NT) void features_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                       const ks_desc* __restrict__ desc, uint32_t num_series,
                                                       uint32_t max_K, float* __restrict__ feat_out,
                                                       uint64_t feat_rows, uint16_t* __restrict__ x0,
                                                       uint32_t SR, LearnWs lw, float* __restrict__ feat_ws) {
-  using S = RowSortShape<NMAX, NT, RB>;
-  __shared__ FeatSmem<NMAX, NT, RB> sm;
+  constexpr int W = NT / kWave;
+  constexpr bool kPrefetch = NB <= 2;
+  __shared__ SelLds sel[W];
+  __shared__ uint32_t red[W];
   const uint32_t s = blockIdx.x;
   if (s >= num_series) return;
   const ks_desc d = desc[s];
-  const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-  if (check_desc(d, num_samples, max_K) || d.N > (uint32_t)NMAX) {
+  const uint32_t tid = threadIdx.x, lane = lane_id();
+  const uint32_t w = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const bool bad = check_desc(d, num_samples, max_K) || d.N > KS_FEATURE_MAX_N;
+  if ((bad ? 1u : feat_batches(d.N)) != (uint32_t)NB) return;
+  if (bad) {
     for (uint32_t q = tid; q < SR * 16; q += NT) x0[(uint64_t)s * SR * 16 + q] = 0;
     if (tid == 0) lw.K[s] = 0;
     return;
   }
   const uint32_t K = d.K, N = d.N;
   const uint64_t slot = (uint64_t)s * SR + 2;
+  SelLds& L = sel[w];
   uint32_t gmin = 0xffffffffu;
-  for (uint32_t i = 0; i < K; ++i) {
-    const uint32_t* row = samples + d.offset + (uint64_t)i * N;
-    uint32_t v[S::E];
-    uint32_t mn = 0xffffffffu, mx = 0;
-    uint64_t s1 = 0, s2 = 0;
-    uint32_t s2h = 0;
-#pragma unroll
-    for (int e = 0; e < S::E; ++e) {
-      const uint32_t j = e * NT + tid;
-      v[e] = j < N ? __builtin_nontemporal_load(row + j) : 0u;
+  Batch cur[NB], nxt[NB];
+  if (w < K) load_row<NB>(cur, samples, d.offset + (uint64_t)w * N, N, lane);
+  for (uint32_t i = w; i < K; i += W) {
+    const uint32_t ni = i + W;
+    if (kPrefetch && ni < K) load_row<NB>(nxt, samples, d.offset + (uint64_t)ni * N, N, lane);
+    uint64_t s1, s2;
+    uint32_t s2h, dec;
+    gmin = min(gmin, feature_row<NB>(L, cur, N, lane, s1, s2, s2h, dec));
+    if (lane == 0) {
+      lw.s1[slot + i] = s1;
+      lw.s2lo[slot + i] = s2;
+      lw.s2hi[slot + i] = s2h;
     }
+    // feature numerators x - m need the series minimum: keep x itself
+    if (lane < 9) feat_ws[(slot + i) * 9 + lane] = __uint_as_float(dec);
+    if (ni < K) {
+      if (kPrefetch) {
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) {
-      const uint32_t j = e * NT + tid;
-      if (j < N) {
-        acc_sample(v[e], mn, s1, s2, s2h);
-        mx = max(mx, v[e]);
+        for (int u = 0; u < NB; ++u) cur[u] = nxt[u];
+      } else {
+        load_row<NB>(cur, samples, d.offset + (uint64_t)ni * N, N, lane);
       }
     }
-    wave_total_64_96(s1, s2, s2h);
-    mn = wave_min_u32(mn);
-    mx = wave_max_u32(mx);
-    if (lane == 0) {
-      sm.red[w * 8 + 0] = mn;
-      sm.red[w * 8 + 1] = mx;
-      sm.red[w * 8 + 2] = (uint32_t)s1;
-      sm.red[w * 8 + 3] = (uint32_t)(s1 >> 32);
-      sm.red[w * 8 + 4] = (uint32_t)s2;
-      sm.red[w * 8 + 5] = (uint32_t)(s2 >> 32);
-      sm.red[w * 8 + 6] = s2h;
-    }
-    __syncthreads();
-    uint32_t rmin = sm.red[0], rmax = sm.red[1];
-    uint64_t t1 = 0, t2 = 0;
-    uint32_t t2h = 0;
-    for (int u = 0; u < S::W; ++u) {
-      rmin = min(rmin, sm.red[u * 8 + 0]);
-      rmax = max(rmax, sm.red[u * 8 + 1]);
-      t1 += ((uint64_t)sm.red[u * 8 + 3] << 32) | sm.red[u * 8 + 2];
-      const uint64_t a = ((uint64_t)sm.red[u * 8 + 5] << 32) | sm.red[u * 8 + 4];
-      const uint64_t b = t2 + a;
-      t2h += sm.red[u * 8 + 6] + (uint32_t)(b < t2);
-      t2 = b;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      lw.s1[slot + i] = t1;
-      lw.s2lo[slot + i] = t2;
-      lw.s2hi[slot + i] = t2h;
-    }
-    gmin = min(gmin, rmin);
-    // sort keys r - rmin; only the range's bit length takes passes
-    const uint32_t range = rmax - rmin;
-    const int bits = range ? 32 - __clz(range) : 0;
-#pragma unroll
-    for (int e = 0; e < S::E; ++e) v[e] -= rmin;
-    const int cur = block_sort_u32(sm, v, N, bits);
-    if (tid < 9) {
-      const uint32_t k = tid + 1;
-      const uint32_t pos = (uint32_t)(((uint64_t)k * (N - 1)) / 10);
-      // feature numerators x - m need the series minimum: keep x itself
-      feat_ws[(slot + i) * 9 + tid] = __uint_as_float(sm.key[cur][pos] + rmin);
-    }
-    __syncthreads();
   }
+  if (lane == 0) red[w] = gmin;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < W; ++u) gmin = min(gmin, red[u]);
   // second sweep: normalise by the series minimum
   const double denom = (double)(gmin > 1 ? gmin : 1u);
   const bool to_user = feat_out && d.aux_offset <= feat_rows && K <= feat_rows - d.aux_offset;

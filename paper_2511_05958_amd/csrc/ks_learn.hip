@@ -31,7 +31,6 @@ void free_learn(LearnBuffers& b) {
 
 namespace {
 
-constexpr uint32_t kFeatNMax = 4096;  // largest N of the feature pass
 constexpr uint32_t kDwGrid = 256;     // workgroups of a weight-gradient reduction
 
 uint32_t slot_rows(uint32_t max_K) { return (max_K + 4 + 15) / 16 * 16; }
@@ -303,8 +302,14 @@ int ks_features(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
   if (int rc = ensure_learn(ctx, (uint64_t)num_series * SR, num_series, false)) return rc;
   hipStream_t st = (hipStream_t)stream;
   LearnBuffers& b = ctx->learn;
-  hipLaunchKernelGGL((ks::features_kernel<kFeatNMax, kNT, kRB>), dim3(num_series), dim3(kNT), 0, st, samples,
-                     num_samples, desc, num_series, max_K, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);
+  // one launch per row length class (1, 2 or 4 load batches per row); each
+  // workgroup whose series belongs to another class returns at once
+  hipLaunchKernelGGL((ks::features_kernel<1, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
+                     num_series, max_K, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);
+  hipLaunchKernelGGL((ks::features_kernel<2, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
+                     num_series, max_K, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);
+  hipLaunchKernelGGL((ks::features_kernel<4, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
+                     num_series, max_K, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "features launch");
   b.stamp_desc = desc;

@@ -75,6 +75,50 @@ def test_features_edge_cases(ctx):
         assert np.array_equal(f[a:a + r.shape[0]], O.features(r)), t
 
 
+def _select_stress_series():
+    """Rows that exercise every row-length class (1, 2 or 4 load batches), rows
+    that start off a 16-byte boundary, and ranges needing 1..5 digit levels."""
+    rng = np.random.default_rng(20251105)
+    out = []
+    Ns = [1, 2, 3, 5, 63, 64, 65, 1023, 1027, 1028, 1029, 2051, 2052, 2053, 4095, 4096]
+    for t, N in enumerate(Ns):
+        K = 3 + t % 4
+        kind = t % 6
+        if kind == 0:  # narrow: one digit level
+            r = rng.integers(500, 500 + 200, (K, N))
+        elif kind == 1:  # latency-like: lognormal plateau, rare 5x outliers (about 13 bits)
+            base = rng.lognormal(np.log(800), 0.08, (K, N))
+            out_m = np.where(rng.random((K, N)) < 0.01, rng.uniform(1, 5, (K, N)), 1.0)
+            r = np.round(base * out_m)
+        elif kind == 2:  # 20-bit range
+            r = rng.integers(1000, 1000 + (1 << 20), (K, N))
+        elif kind == 3:  # 27-bit range, heavy duplicates
+            r = rng.choice(np.array([7, 7, 7, 9, 1 << 26, (1 << 27) - 1]), (K, N))
+        elif kind == 4:  # full 32-bit range
+            r = rng.integers(0, 1 << 32, (K, N), dtype=np.uint64)
+        else:  # two clusters far apart: deciles in distinct groups at every level
+            r = np.where(rng.random((K, N)) < 0.5, rng.integers(100, 140, (K, N)), rng.integers(3_000_000, 3_000_050, (K, N)))
+        out.append(np.asarray(r, np.uint64).astype(np.uint32))
+    return out
+
+
+def test_features_select_stress(ctx):
+    ss = _select_stress_series()
+    parts, offs, off = [], [], 0
+    for r in ss:
+        off += 1  # odd offsets: rows start at every alignment
+        offs.append(off)
+        parts.append(np.zeros(1, np.uint32))
+        parts.append(r.ravel())
+        off += r.size
+    x = np.concatenate(parts)
+    d = P.make_desc(offs, [r.shape[0] for r in ss], [r.shape[1] for r in ss])
+    f = gpu_features(ctx, x, d, 64)
+    for t, r in enumerate(ss):
+        a = int(d[t]["aux_offset"])
+        assert np.array_equal(f[a:a + r.shape[0]], O.features(r)), (t, r.shape)
+
+
 def test_forward_matches_oracle(ctx):
     import torch
 
