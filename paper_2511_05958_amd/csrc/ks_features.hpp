@@ -31,16 +31,19 @@ struct LearnWs {
 // (group << s) | (its s low bits), s the bits still unresolved, with group
 // kSelNone for keys outside every group, so the next level's bin is the key
 // shifted right by the next s. Histograms are LDS counters per (group, digit)
-// bin; the bins of group kSelNone are counted but never read.
+// bin; keys whose bin lies past the live groups issue no LDS access (such
+// keys would pile onto a few addresses and serialise the atomics).
 
-constexpr uint32_t kSelW0 = 8;     // bits of the level-0 digit
+constexpr uint32_t kSelW0 = 10;    // bits of the level-0 digit (1024 bins fit the histogram)
 constexpr uint32_t kSelW = 7;      // bits of every later digit
 constexpr uint32_t kSelNone = 9;   // group of keys outside every target's prefix
 
-struct SelLds {
+struct __align__(16) SelLds {
   uint32_t hist[(kSelNone + 1) << kSelW];  // bin counts, then exclusive prefixes
   uint8_t tab[(kSelNone + 1) << kSelW];    // bin -> group at the next level
 };
+static_assert((1u << kSelW0) <= ((kSelNone + 1) << kSelW), "level-0 bins fit the histogram");
+static_assert((((kSelNone << kSelW) + 255u) & ~255u) <= ((kSelNone + 1) << kSelW), "padded live bins fit");
 
 // LDS accesses of one wave are performed in order; this keeps the compiler
 // from moving them across the point where lanes exchange data through LDS.
@@ -50,9 +53,34 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Exclusive prefix sums, in place, over hist[0, 256 nblk), bins in order. Lane
+// l owns bins 256 i + 4 l .. 256 i + 4 l + 3 of block i, so every access is a
+// conflict-free 16-byte one; two blocks share one wave scan, packed as 16-bit
+// halves (a wave holds fewer than 2^16 keys, so no half carries into the next).
+__device__ __forceinline__ void wave_excl_prefix(uint32_t* hist, uint32_t nblk, uint32_t lane) {
+  uint32_t base = 0;
+  for (uint32_t i = 0; i < nblk; i += 2) {
+    const bool two = i + 1 < nblk;
+    u32x4* pa = reinterpret_cast<u32x4*>(hist + 256u * i + 4u * lane);
+    u32x4* pc = reinterpret_cast<u32x4*>(hist + 256u * (i + 1) + 4u * lane);
+    const u32x4 a = *pa;
+    const u32x4 c = two ? *pc : u32x4{0u, 0u, 0u, 0u};
+    const uint32_t sa = a.x + a.y + a.z + a.w, sc = c.x + c.y + c.z + c.w;
+    const uint32_t incl = wave_incl_scan(sa | (sc << 16));
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+    const uint32_t ea = base + (incl & 0xffffu) - sa;
+    const uint32_t basec = base + (tot & 0xffffu);
+    const uint32_t ec = basec + (incl >> 16) - sc;
+    *pa = u32x4{ea, ea + a.x, ea + a.x + a.y, ea + a.x + a.y + a.z};
+    if (two) *pc = u32x4{ec, ec + c.x, ec + c.x + c.y, ec + c.x + c.y + c.z};
+    base = basec + (tot >> 16);
+  }
+}
+
 // k[]: this lane's keys (values - row minimum; slots without a sample hold
-// 2^b - 1, which sorts at or after the row maximum), b >= 1 the bit length of
-// the row's range; the keys are consumed. Lane j < 9 returns the key of rank
+// 0xffffffff, which lies past every level-0 bin unless b = 32, and then sorts
+// at or after the row maximum), b >= 1 the bit length of the row's range; the
+// keys are consumed. Lane j < 9 returns the key of rank
 // floor((j + 1)(N - 1) / 10).
 template <int V>
 __device__ __forceinline__ uint32_t wave_deciles(SelLds& L, uint32_t (&k)[V], uint32_t b, uint32_t N,
@@ -64,27 +92,18 @@ __device__ __forceinline__ uint32_t wave_deciles(SelLds& L, uint32_t (&k)[V], ui
   for (;;) {
     const uint32_t w = min(sprev, wmax);
     const uint32_t s = sprev - w;
-    const uint32_t T = G << w;  // live bins: groups 0..G-1
-    for (uint32_t q = lane; q < T; q += kWave) L.hist[q] = 0u;
+    const uint32_t nblk = ((G << w) + 255u) >> 8;  // 256-bin blocks covering groups 0..G-1
+    for (uint32_t i = 0; i < nblk; ++i)
+      *reinterpret_cast<u32x4*>(L.hist + 256u * i + 4u * lane) = u32x4{0u, 0u, 0u, 0u};
     wave_lds_sync();
+    const uint32_t live = G << w;  // bins of groups 0..G-1; keys past them are not counted
 #pragma unroll
     for (int e = 0; e < V; ++e) {
-      atomicAdd(&L.hist[k[e] >> s], 1u);
-      if (e % 8 == 7) __builtin_amdgcn_sched_barrier(0);  // bounds the addresses in flight
+      const uint32_t x = k[e] >> s;
+      if (x < live) atomicAdd(&L.hist[x], 1u);
     }
     wave_lds_sync();
-    // exclusive prefix over the live bins, lane-contiguous chunks
-    const uint32_t C = (T + kWave - 1) / kWave, b0 = lane * C;
-    uint32_t sum = 0;
-    for (uint32_t c = 0; c < C; ++c)
-      if (b0 + c < T) sum += L.hist[b0 + c];
-    uint32_t run = wave_incl_scan(sum) - sum;
-    for (uint32_t c = 0; c < C; ++c)
-      if (b0 + c < T) {
-        const uint32_t h = L.hist[b0 + c];
-        L.hist[b0 + c] = run;
-        run += h;
-      }
+    wave_excl_prefix(L.hist, nblk, lane);
     wave_lds_sync();
     // each target: the last bin of its group whose prefix is <= its rank
     uint32_t x = 0;
@@ -105,7 +124,7 @@ __device__ __forceinline__ uint32_t wave_deciles(SelLds& L, uint32_t (&k)[V], ui
     const bool fresh = tl && (lane == 0 || x != prev);
     const uint64_t m = ballot(fresh);
     const uint32_t id = mbcnt(m) - (fresh ? 0u : 1u);
-    const uint32_t words = ((wmax == kSelW0 ? 1u : kSelNone + 1) << w) / 4u;  // bins incl. group kSelNone
+    const uint32_t words = live / 4u;
     uint32_t* tw = reinterpret_cast<uint32_t*>(L.tab);
     for (uint32_t q = lane; q < words; q += kWave) tw[q] = kSelNone * 0x01010101u;
     wave_lds_sync();
@@ -118,8 +137,9 @@ __device__ __forceinline__ uint32_t wave_deciles(SelLds& L, uint32_t (&k)[V], ui
     const uint32_t low = (1u << s) - 1u;
 #pragma unroll
     for (int e = 0; e < V; ++e) {
-      k[e] = ((uint32_t)L.tab[k[e] >> s2] << s) | (k[e] & low);
-      if (e % 8 == 7) __builtin_amdgcn_sched_barrier(0);  // bounds the lookups in flight
+      const uint32_t x = k[e] >> s2;
+      const uint32_t g = x < live ? (uint32_t)L.tab[x] : kSelNone;
+      k[e] = (g << s) | (k[e] & low);
     }
     wave_lds_sync();
     tg = id;
@@ -148,50 +168,109 @@ __device__ __forceinline__ void load_row(Batch (&B)[NB], const uint32_t* __restr
   }
 }
 
+// Wave totals of a 32-bit and a 64-bit per-lane sum, returned wave-uniform.
+__device__ __forceinline__ void wave_total_32_64(uint32_t& a, uint64_t& c) {
+  a += dpp<kDppXor1>(a);
+  dpp_add64<kDppXor1>(c);
+  a += dpp<kDppXor2>(a);
+  dpp_add64<kDppXor2>(c);
+  a += dpp<kDppHalfMirror>(a);
+  dpp_add64<kDppHalfMirror>(c);
+  a += dpp<kDppMirror>(a);
+  dpp_add64<kDppMirror>(c);
+  a += dpp<kDppBcast15, 0xA>(a);
+  dpp_add64<kDppBcast15, 0xA>(c);
+  a += dpp<kDppBcast31, 0xC>(a);
+  dpp_add64<kDppBcast31, 0xC>(c);
+  a = (uint32_t)__builtin_amdgcn_readlane((int)a, 63);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)c, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(c >> 32), 63);
+  c = ((uint64_t)hi << 32) | lo;
+}
+
+// Largest row range bit length for which a lane's V keys k < 2^b have
+// sum k^2 < 2^32 (and k < 2^24, the 24-bit multiplier's operand range).
+template <int V>
+__host__ __device__ constexpr uint32_t fast_moment_bits() {
+  uint32_t b = 0;
+  while (b < 24 && (uint64_t)V * (((1ull << (b + 1)) - 1) * ((1ull << (b + 1)) - 1)) < (1ull << 32)) ++b;
+  return b;
+}
+
 // One row: moments (sum r, sum r^2), minimum and the nine deciles (lanes 0..8).
+// With the row minimum m known first, rows of a small range accumulate the
+// keys k = r - m in 32 bits (sum k, sum k^2 by the 24-bit multiplier) and
+// recover sum r = sum k + N m and sum r^2 = sum k^2 + 2 m sum k + N m^2 once;
+// wider rows take the 96-bit accumulation of the raw samples.
 template <int NB>
 __device__ __forceinline__ uint32_t feature_row(SelLds& L, const Batch (&B)[NB], uint32_t N, uint32_t lane,
                                                 uint64_t& s1, uint64_t& s2, uint32_t& s2h, uint32_t& dec) {
+  constexpr int V = 17 * NB;
   uint32_t mn = 0xffffffffu, mx = 0u;
-  s1 = 0;
-  s2 = 0;
-  s2h = 0;
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (B[u].m & (1u << q)) {
-        acc_quad(B[u].q[q], mn, s1, s2, s2h);
+        mn = min(mn, min(min(B[u].q[q].x, B[u].q[q].y), min(B[u].q[q].z, B[u].q[q].w)));
         mx = max(mx, max(max(B[u].q[q].x, B[u].q[q].y), max(B[u].q[q].z, B[u].q[q].w)));
       }
     if (B[u].m & 16u) {
-      acc_sample(B[u].x, mn, s1, s2, s2h);
+      mn = min(mn, B[u].x);
       mx = max(mx, B[u].x);
     }
   }
-  wave_total_64_96(s1, s2, s2h);
   const uint32_t rmin = wave_min_u32(mn), rmax = wave_max_u32(mx);
   const uint32_t range = rmax - rmin;
   const uint32_t b = range ? 32u - __clz(range) : 0u;
-  if (b == 0) {
-    dec = rmin;
-    return rmin;
-  }
-  const uint32_t kmax = 0xffffffffu >> (32u - b);
-  uint32_t k[17 * NB];
+  constexpr uint32_t kEmpty = 0xffffffffu;  // key of a slot without a sample
+  uint32_t k[V];
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const bool v = (B[u].m >> q) & 1u;
-      k[u * 17 + q * 4 + 0] = v ? B[u].q[q].x - rmin : kmax;
-      k[u * 17 + q * 4 + 1] = v ? B[u].q[q].y - rmin : kmax;
-      k[u * 17 + q * 4 + 2] = v ? B[u].q[q].z - rmin : kmax;
-      k[u * 17 + q * 4 + 3] = v ? B[u].q[q].w - rmin : kmax;
+      k[u * 17 + q * 4 + 0] = v ? B[u].q[q].x - rmin : kEmpty;
+      k[u * 17 + q * 4 + 1] = v ? B[u].q[q].y - rmin : kEmpty;
+      k[u * 17 + q * 4 + 2] = v ? B[u].q[q].z - rmin : kEmpty;
+      k[u * 17 + q * 4 + 3] = v ? B[u].q[q].w - rmin : kEmpty;
     }
-    k[u * 17 + 16] = (B[u].m & 16u) ? B[u].x - rmin : kmax;
+    k[u * 17 + 16] = (B[u].m & 16u) ? B[u].x - rmin : kEmpty;
   }
-  dec = wave_deciles<17 * NB>(L, k, b, N, lane) + rmin;
+  if (b <= fast_moment_bits<V>()) {
+    uint32_t t1 = 0;
+    uint32_t t2 = 0;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const uint32_t z = k[e] == kEmpty ? 0u : k[e];
+      t1 += z;
+      t2 += __umul24(z, z);
+    }
+    uint64_t t2w = t2;
+    wave_total_32_64(t1, t2w);
+    const u128 q2 = (u128)t2w + (u128)(2ull * rmin) * t1 + (u128)((uint64_t)rmin * rmin) * N;
+    s1 = (uint64_t)t1 + (uint64_t)rmin * N;
+    s2 = (uint64_t)q2;
+    s2h = (uint32_t)(q2 >> 64);
+  } else {
+    uint32_t unused = 0xffffffffu;
+    s1 = 0;
+    s2 = 0;
+    s2h = 0;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (B[u].m & (1u << q)) acc_quad(B[u].q[q], unused, s1, s2, s2h);
+      if (B[u].m & 16u) acc_sample(B[u].x, unused, s1, s2, s2h);
+    }
+    wave_total_64_96(s1, s2, s2h);
+  }
+  if (b == 0) {
+    dec = rmin;
+    return rmin;
+  }
+  dec = wave_deciles<V>(L, k, b, N, lane) + rmin;
   return rmin;
 }
 

@@ -119,6 +119,43 @@ def test_features_select_stress(ctx):
         assert np.array_equal(f[a:a + r.shape[0]], O.features(r)), (t, r.shape)
 
 
+def test_refine_moments_all_classes(ctx):
+    """The feature pass's row moments (both accumulation paths, every row class)
+    drive the exact refine; with zero confidence every series falls back to the
+    full-range choice, which must equal the oracle's scan bit for bit."""
+    import torch
+
+    ss = _select_stress_series()
+    parts, offs, off = [], [], 0
+    for r in ss:
+        off += 3
+        offs.append(off)
+        parts.append(np.zeros(3, np.uint32))
+        parts.append(r.ravel())
+        off += r.size
+    x = np.concatenate(parts)
+    d = P.make_desc(offs, [r.shape[0] for r in ss], [r.shape[1] for r in ss])
+    n = len(d)
+    s_d, d_d = P.to_device(x), P.to_device(d)
+    rows = int(d["K"].astype(np.int64).sum())
+    feats = torch.empty(rows * 9, dtype=torch.float32, device="cuda")
+    P.ks_features(ctx.handle, s_d, d_d, n, 64, feats)
+    prm = P.ks_params_init(0.05)
+    prm.max_K = 64
+    prm.tau = 0.5
+    prop = torch.ones(n, dtype=torch.int32, device="cuda")
+    conf = torch.zeros(n, dtype=torch.float32, device="cuda")
+    out = P.empty_results(n)
+    P.ks_refine(ctx.handle, d_d, n, len(x), prop, conf, prm, out)
+    torch.cuda.synchronize()
+    g = P.results_to_numpy(out)
+    for t, r in enumerate(ss):
+        ref = O.scan_series(r)
+        assert (g[t]["cp"], g[t]["U"], g[t]["n"], g[t]["m"]) == (ref["cp"], ref["U"], ref["n"], ref["m"]), t
+        assert g[t]["p"] == ref["p"] or abs(g[t]["p"] - ref["p"]) <= 1e-12 * ref["p"], t
+        assert g[t]["flags"] & P.KS_FALLBACK
+
+
 def test_forward_matches_oracle(ctx):
     import torch
 
