@@ -134,6 +134,170 @@ __global__ __launch_bounds__(NTC) void conv_kernel(const uint16_t* __restrict__ 
   }
 }
 
+// ------------------------------------------------------------ fused forward
+// The whole network over tiles of FT rows, for inference. A tile's frame is
+// its FT rows plus FH = 8 halo rows on each side (2 per layer): frame row f is
+// sequence row r0 - FH + f. Every layer computes all FR = FT + 16 frame rows
+// (nine 16-row MFMA blocks); the rows within 2l of the frame's ends are wrong
+// after layer l (their inputs fall off the frame) but never reach the rows
+// [FH, FH + FT) whose logits are written. Activations stay in LDS as bf16,
+// zeroed on rows outside their series exactly as the per-layer kernels write
+// them; the accumulation order over j equals the per-layer kernels', so the
+// logits match theirs bit for bit. Wave w owns output channels 16w .. 16w + 15
+// of layers 0..2 and keeps their weights in registers for the whole launch.
+constexpr int FT = 128;
+constexpr int FH = 8;
+constexpr int FR = FT + 2 * FH;  // 144
+constexpr int FBLK = FR / 16;    // 9 row blocks
+constexpr int FST = 64 + 8;      // LDS row stride of a 64-channel activation buffer (bf16)
+constexpr int FXS = 16 + 8;      // LDS row stride of the 16-channel input buffer
+constexpr int FW3 = 320 + 8;     // LDS row stride of the last layer's weights
+
+struct FusedSmem {
+  uint16_t act[2][(FR + 4) * FST];  // buffer row f + 2 holds frame row f; rows 0, 1, FR + 2, FR + 3 stay zero
+  uint16_t x[(FR + 4) * FXS];
+  uint16_t w3[2 * FW3];             // row 0: W3[0][j]; row 1: zeros (output channels 1..15)
+  uint8_t valid[FR];
+};
+
+// One 64-output-channel layer over the frame for this wave's 16 channels:
+// out[f][16 w + m] = bf16(relu(b + sum_j W[16 w + m][j] in[f + k - 2][i])) on
+// valid rows, 0 elsewhere (j = k CIN + i).
+template <int CIN, int NQ>
+__device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ in, int ist, const u32x4 (&B)[NQ],
+                                            float bias, uint16_t* __restrict__ out, const uint8_t* __restrict__ valid,
+                                            uint32_t w, uint32_t m, uint32_t kg) {
+  constexpr int J = KW * CIN;
+#pragma unroll 1
+  for (int g = 0; g < FBLK; g += 3) {
+    f32x4 acc[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // A operands one k-step ahead of the MFMAs; the scheduling barrier keeps
+    // the compiler from hoisting every step's loads (and their registers)
+    auto load_a = [&](int q, u32x4 (&a)[3]) {
+      const int j0 = q * 32 + (int)kg * 8;
+      const int k = j0 / CIN, i0 = j0 - k * CIN;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        // frame row 16 (g + t) + m, tap k: buffer row 16 (g + t) + m + k
+        a[t] = (NQ * 32 <= J || j0 < J) ? *reinterpret_cast<const u32x4*>(&in[((g + t) * 16 + (int)m + k) * ist + i0])
+                                        : u32x4{0u, 0u, 0u, 0u};
+      }
+    };
+    u32x4 a0[3], a1[3];
+    load_a(0, a0);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      u32x4(&cur)[3] = (q & 1) ? a1 : a0;
+      u32x4(&nxt)[3] = (q & 1) ? a0 : a1;
+      if (q + 1 < NQ) load_a(q + 1, nxt);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[t] = mfma16(cur[t], B[q], acc[t]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int f = (g + t) * 16 + (int)kg * 4 + e;
+        out[(f + 2) * FST + w * 16 + m] = valid[f] ? f2bf(relu(acc[t][e] + bias)) : (uint16_t)0;
+      }
+  }
+}
+
+// x0 [rows][16] bf16 (channels 11..15 zero), wf[l] as for conv_kernel,
+// logits [rows] fp32 (0 on rows outside every series).
+__global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(3))) void fused_forward_kernel(const uint16_t* __restrict__ x0, uint64_t rows,
+                                                            uint32_t SR, const uint32_t* __restrict__ Ks,
+                                                            const uint16_t* __restrict__ w0,
+                                                            const uint16_t* __restrict__ w1,
+                                                            const uint16_t* __restrict__ w2,
+                                                            const uint16_t* __restrict__ w3,
+                                                            const float* __restrict__ b0, const float* __restrict__ b1,
+                                                            const float* __restrict__ b2, const float* __restrict__ b3,
+                                                            float* __restrict__ logits) {
+  __shared__ __align__(16) FusedSmem sm;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+  const uint32_t m = lane & 15u, kg = lane >> 4;
+  const uint32_t o = w * 16 + m;
+  // B operands of this wave's channels: W[o][32 q + 8 kg .. + 7]
+  u32x4 B0[3], B1[10], B2[10];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int j0 = q * 32 + (int)kg * 8;
+    B0[q] = j0 < 80 ? *reinterpret_cast<const u32x4*>(w0 + o * 80 + j0) : u32x4{0u, 0u, 0u, 0u};
+  }
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    B1[q] = *reinterpret_cast<const u32x4*>(w1 + o * 320 + q * 32 + kg * 8);
+    B2[q] = *reinterpret_cast<const u32x4*>(w2 + o * 320 + q * 32 + kg * 8);
+  }
+  const float bias0 = b0[o], bias1 = b1[o], bias2 = b2[o], bias3 = b3[0];
+  for (uint32_t q = tid; q < 2u * FW3; q += NTC) sm.w3[q] = q < 320u ? w3[q] : (uint16_t)0;
+  for (uint32_t q = tid; q < 4u * FST; q += NTC) {
+    const uint32_t r = q / FST, c = q - r * FST, br = r < 2 ? r : FR + r;
+    sm.act[0][br * FST + c] = 0;
+    sm.act[1][br * FST + c] = 0;
+  }
+  for (uint32_t q = tid; q < 4u * FXS; q += NTC) {
+    const uint32_t r = q / FXS, c = q - r * FXS, br = r < 2 ? r : FR + r;
+    sm.x[br * FXS + c] = 0;
+  }
+  const uint64_t ntiles = (rows + FT - 1) / FT;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t r0 = (int64_t)(tile * FT);
+    __syncthreads();
+    for (uint32_t f = tid; f < (uint32_t)FR; f += NTC) {
+      const int64_t row = r0 - FH + (int64_t)f;
+      sm.valid[f] = row >= 0 && row_valid((uint64_t)row, rows, SR, Ks);
+    }
+    for (uint32_t q = tid; q < 2u * FR; q += NTC) {
+      const uint32_t f = q >> 1, h = q & 1u;
+      const int64_t row = r0 - FH + (int64_t)f;
+      u32x4 v = u32x4{0u, 0u, 0u, 0u};
+      if (row >= 0 && (uint64_t)row < rows) v = *reinterpret_cast<const u32x4*>(x0 + (uint64_t)row * 16 + h * 8);
+      *reinterpret_cast<u32x4*>(&sm.x[(f + 2) * FXS + h * 8]) = v;
+    }
+    __syncthreads();
+    fused_layer<16, 3>(sm.x, FXS, B0, bias0, sm.act[0], sm.valid, w, m, kg);
+    __syncthreads();
+    fused_layer<64, 10>(sm.act[0], FST, B1, bias1, sm.act[1], sm.valid, w, m, kg);
+    __syncthreads();
+    fused_layer<64, 10>(sm.act[1], FST, B2, bias2, sm.act[0], sm.valid, w, m, kg);
+    __syncthreads();
+    // last layer (one output channel): wave w takes row blocks w, w + 4, w + 8
+    const uint16_t* w3row = &sm.w3[m == 0 ? 0 : FW3];
+    for (int blk = (int)w; blk < FBLK; blk += 4) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+      auto load_ab = [&](int q, u32x4& a, u32x4& b) {
+        const int j0 = q * 32 + (int)kg * 8;
+        const int k = j0 / 64, i0 = j0 - k * 64;
+        a = *reinterpret_cast<const u32x4*>(&sm.act[0][(blk * 16 + (int)m + k) * FST + i0]);
+        b = *reinterpret_cast<const u32x4*>(&w3row[j0]);
+      };
+      u32x4 a0, b0, a1, b1;
+      load_ab(0, a0, b0);
+#pragma unroll
+      for (int q = 0; q < 10; ++q) {
+        u32x4& ca = (q & 1) ? a1 : a0;
+        u32x4& cb = (q & 1) ? b1 : b0;
+        if (q + 1 < 10) load_ab(q + 1, (q & 1) ? a0 : a1, (q & 1) ? b0 : b1);
+        acc = mfma16(ca, cb, acc);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (m == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int f = blk * 16 + (int)kg * 4 + e;
+          const int64_t row = r0 - FH + f;
+          if (f >= FH && f < FH + FT && (uint64_t)row < rows) logits[row] = sm.valid[f] ? acc[e] + bias3 : 0.0f;
+        }
+      }
+    }
+  }
+}
+
 // Weight gradient partials of one layer:
 //   dW[o][j] = sum_rows dY[row][o] X[row + k - 2][i]   (j = k CIN + i)
 //   db[o]    = sum_rows dYf[row][o]

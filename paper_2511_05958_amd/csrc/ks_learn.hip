@@ -83,7 +83,8 @@ uint32_t conv_grid(const ks_ctx* c, uint64_t rows) {
   return (uint32_t)(tiles < cap ? (tiles ? tiles : 1) : cap);
 }
 
-// The network forward over the slot rows: x0 -> a1 -> a2 -> a3 -> logits.
+// The network forward over the slot rows, one launch per layer, keeping the
+// activations a1..a3 for the backward pass: x0 -> a1 -> a2 -> a3 -> logits.
 hipError_t forward(ks_ctx* c, const ks_model* m, uint64_t rows, uint32_t SR, hipStream_t st) {
   LearnBuffers& b = c->learn;
   const uint32_t g = conv_grid(c, rows);
@@ -95,6 +96,17 @@ hipError_t forward(ks_ctx* c, const ks_model* m, uint64_t rows, uint32_t SR, hip
                      m->b[2], rows, SR, b.K, b.act[2], (float*)nullptr, (const uint16_t*)nullptr);
   hipLaunchKernelGGL((C::conv_kernel<64, 16, C::EPI_LOGIT>), dim3(g), dim3(C::NTC), 0, st, b.act[2], m->wf[3],
                      m->b[3], rows, SR, b.K, (uint16_t*)nullptr, b.logits, (const uint16_t*)nullptr);
+  return hipGetLastError();
+}
+
+// Inference: the whole network in one launch, activations kept in LDS.
+hipError_t forward_infer(ks_ctx* c, const ks_model* m, uint64_t rows, uint32_t SR, hipStream_t st) {
+  LearnBuffers& b = c->learn;
+  const uint64_t tiles = (rows + C::FT - 1) / C::FT;
+  const uint64_t cap = (uint64_t)c->num_cus * 3;  // three 51 KB workgroups per CU
+  const uint32_t g = (uint32_t)(tiles < cap ? (tiles ? tiles : 1) : cap);
+  hipLaunchKernelGGL(C::fused_forward_kernel, dim3(g), dim3(C::NTC), 0, st, b.x0, rows, SR, b.K, m->wf[0], m->wf[1],
+                     m->wf[2], m->wf[3], m->b[0], m->b[1], m->b[2], m->b[3], b.logits);
   return hipGetLastError();
 }
 
@@ -338,7 +350,7 @@ int ks_cnn_forward(ks_ctx* ctx, const ks_model* model, const float* features, ui
   b.stamp_valid = false;  // the slot buffers no longer hold a proposal pass
   hipLaunchKernelGGL(C::pack_features_kernel, dim3(num_series), dim3(C::NTC), 0, st, features, feature_rows, desc,
                      num_series, max_K, SR, b.x0, b.K);
-  hipError_t e = forward(ctx, model, rows, SR, st);
+  hipError_t e = forward_infer(ctx, model, rows, SR, st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(C::unpack_logits_kernel, dim3(num_series), dim3(C::NTC), 0, st, b.logits, desc, num_series,
                        SR, b.K, logits, logit_rows);
@@ -361,7 +373,7 @@ int ks_propose(ks_ctx* ctx, const ks_model* model, const uint32_t* samples, uint
   hipStream_t st = (hipStream_t)stream;
   LearnBuffers& b = ctx->learn;
   const uint32_t SR = b.stamp_SR;
-  hipError_t e = forward(ctx, model, (uint64_t)num_series * SR, SR, st);
+  hipError_t e = forward_infer(ctx, model, (uint64_t)num_series * SR, SR, st);
   if (e == hipSuccess) {
     const uint32_t per = C::NTC / 64;
     hipLaunchKernelGGL(C::softmax_kernel, dim3((num_series + per - 1) / per), dim3(C::NTC), 0, st, b.logits,
