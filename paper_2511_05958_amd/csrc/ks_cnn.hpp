@@ -142,8 +142,8 @@ __global__ __launch_bounds__(NTC) void conv_kernel(const uint16_t* __restrict__ 
 // after layer l (their inputs fall off the frame) but never reach the rows
 // [FH, FH + FT) whose logits are written. Activations stay in LDS as bf16,
 // zeroed on rows outside their series exactly as the per-layer kernels write
-// them; the accumulation order over j equals the per-layer kernels', so the
-// logits match theirs bit for bit. Wave w owns output channels 16w .. 16w + 15
+// them, and each output accumulates over j in the per-layer kernels' order
+// (same MFMA steps, bias added last). Wave w owns output channels 16w .. 16w + 15
 // of layers 0..2 and keeps their weights in registers for the whole launch.
 constexpr int FT = 128;
 constexpr int FH = 8;
