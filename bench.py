@@ -130,6 +130,42 @@ def learned_leg(args, ctx, batch, samples, desc, out_plain, prm, stream, res_pla
     }
 
 
+# Sources of the scan kernels (plain path); their hash ties a recorded HBM
+# traffic figure to the code it was measured on.
+SCAN_SOURCES = ["include/ks.h", "paper_2511_05958_amd/csrc/ks_wave.hpp", "paper_2511_05958_amd/csrc/ks_scan.hpp",
+                "paper_2511_05958_amd/csrc/ks_persist.hpp", "paper_2511_05958_amd/csrc/ks_ctx.hpp",
+                "paper_2511_05958_amd/csrc/ks_api.hip"]
+TRAFFIC_FILE = os.path.join("profiles", "hbm_traffic.txt")
+
+
+def scan_sources_sha() -> str:
+    import hashlib
+
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in SCAN_SOURCES:
+        h.update(f.encode())
+        h.update(b"\0")
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch measured by rocprofv3 for this kernel and workload on
+    the current sources, or None (no record, or the kernel changed since)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    sha = scan_sources_sha()
+    with open(path) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 5 and not line.startswith("#") and f[0] == kernel and f[1] == workload and f[2] == sha:
+                return int(f[3]) + int(f[4])
+    return None
+
+
 def copy_calibration(args) -> int:
     import torch
 
@@ -228,6 +264,7 @@ def main() -> int:
     res = P.results_to_numpy(out)
     bad = int(np.count_nonzero(res["flags"] & (P.KS_BAD_SHAPE | P.KS_OUT_OF_RANGE)))
     bytes_per_launch = batch.sample_bytes + 48 * n
+    kernel_name = "ks::scan_persistent" if chosen["mode"] == P.KS_LAUNCH_PERSISTENT else "ks::scan_kernel"
     achieved = bytes_per_launch / avg_kern_s / 1e9
     line = {
         "metric": "KS change-point series/s at 1 GPU (plain exact scan), % HBM roofline",
@@ -258,8 +295,8 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "ks::scan_persistent" if chosen["mode"] == P.KS_LAUNCH_PERSISTENT else "ks::scan_kernel",
+            "traffic": recorded_traffic(kernel_name, args.workload),
+            "kernel": kernel_name,
             "kernel_ms": avg_kern_s * 1e3,
         },
     }
