@@ -101,6 +101,7 @@ __device__ __forceinline__ uint32_t wave_deciles(SelLds& L, uint32_t (&k)[V], ui
     for (int e = 0; e < V; ++e) {
       const uint32_t x = k[e] >> s;
       if (x < live) atomicAdd(&L.hist[x], 1u);
+      if (V > 17 && e % 17 == 16) __builtin_amdgcn_sched_barrier(0);  // bounds the addresses in flight
     }
     wave_lds_sync();
     wave_excl_prefix(L.hist, nblk, lane);
@@ -137,9 +138,11 @@ __device__ __forceinline__ uint32_t wave_deciles(SelLds& L, uint32_t (&k)[V], ui
     const uint32_t low = (1u << s) - 1u;
 #pragma unroll
     for (int e = 0; e < V; ++e) {
+      // unconditional read at a clamped bin (reads of one address broadcast)
       const uint32_t x = k[e] >> s2;
-      const uint32_t g = x < live ? (uint32_t)L.tab[x] : kSelNone;
-      k[e] = (g << s) | (k[e] & low);
+      const uint32_t t = L.tab[min(x, live - 1u)];
+      k[e] = ((x < live ? t : kSelNone) << s) | (k[e] & low);
+      if (V > 17 && e % 17 == 16) __builtin_amdgcn_sched_barrier(0);  // bounds the lookups in flight
     }
     wave_lds_sync();
     tg = id;
@@ -223,28 +226,27 @@ __device__ __forceinline__ uint32_t feature_row(SelLds& L, const Batch (&B)[NB],
   const uint32_t rmin = wave_min_u32(mn), rmax = wave_max_u32(mx);
   const uint32_t range = rmax - rmin;
   const uint32_t b = range ? 32u - __clz(range) : 0u;
-  constexpr uint32_t kEmpty = 0xffffffffu;  // key of a slot without a sample
-  uint32_t k[V];
-#pragma unroll
-  for (int u = 0; u < NB; ++u) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const bool v = (B[u].m >> q) & 1u;
-      k[u * 17 + q * 4 + 0] = v ? B[u].q[q].x - rmin : kEmpty;
-      k[u * 17 + q * 4 + 1] = v ? B[u].q[q].y - rmin : kEmpty;
-      k[u * 17 + q * 4 + 2] = v ? B[u].q[q].z - rmin : kEmpty;
-      k[u * 17 + q * 4 + 3] = v ? B[u].q[q].w - rmin : kEmpty;
-    }
-    k[u * 17 + 16] = (B[u].m & 16u) ? B[u].x - rmin : kEmpty;
-  }
+  // moments first, from the raw samples, so that the keys can take the
+  // samples' registers afterwards
   if (b <= fast_moment_bits<V>()) {
     uint32_t t1 = 0;
     uint32_t t2 = 0;
-#pragma unroll
-    for (int e = 0; e < V; ++e) {
-      const uint32_t z = k[e] == kEmpty ? 0u : k[e];
+    auto acc = [&](bool v, uint32_t x) {
+      const uint32_t z = v ? x - rmin : 0u;
       t1 += z;
       t2 += __umul24(z, z);
+    };
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool v = (B[u].m >> q) & 1u;
+        acc(v, B[u].q[q].x);
+        acc(v, B[u].q[q].y);
+        acc(v, B[u].q[q].z);
+        acc(v, B[u].q[q].w);
+      }
+      acc((B[u].m & 16u) != 0u, B[u].x);
     }
     uint64_t t2w = t2;
     wave_total_32_64(t1, t2w);
@@ -266,6 +268,20 @@ __device__ __forceinline__ uint32_t feature_row(SelLds& L, const Batch (&B)[NB],
     }
     wave_total_64_96(s1, s2, s2h);
   }
+  constexpr uint32_t kEmpty = 0xffffffffu;  // key of a slot without a sample
+  uint32_t k[V];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool v = (B[u].m >> q) & 1u;
+      k[u * 17 + q * 4 + 0] = v ? B[u].q[q].x - rmin : kEmpty;
+      k[u * 17 + q * 4 + 1] = v ? B[u].q[q].y - rmin : kEmpty;
+      k[u * 17 + q * 4 + 2] = v ? B[u].q[q].z - rmin : kEmpty;
+      k[u * 17 + q * 4 + 3] = v ? B[u].q[q].w - rmin : kEmpty;
+    }
+    k[u * 17 + 16] = (B[u].m & 16u) ? B[u].x - rmin : kEmpty;
+  }
   if (b == 0) {
     dec = rmin;
     return rmin;
@@ -286,13 +302,13 @@ __host__ __device__ constexpr uint32_t feat_batches(uint32_t N) {
 // (nullable, rows at aux_offset), the network input rows (bf16, 16 channels,
 // 11 used) at row slot s * SR + 2 + i, and the refine workspace.
 template <int NB, int NT>
-__global__ __launch_bounds__(NT) void features_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 : 1))) void features_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                       const ks_desc* __restrict__ desc, uint32_t num_series,
                                                       uint32_t max_K, float* __restrict__ feat_out,
                                                       uint64_t feat_rows, uint16_t* __restrict__ x0,
                                                       uint32_t SR, LearnWs lw, float* __restrict__ feat_ws) {
   constexpr int W = NT / kWave;
-  constexpr bool kPrefetch = NB <= 2;
+  constexpr bool kPrefetch = false;  // measured: occupancy hides the row loads better than a prefetch buffer
   __shared__ SelLds sel[W];
   __shared__ uint32_t red[W];
   const uint32_t s = blockIdx.x;
