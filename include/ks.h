@@ -295,6 +295,42 @@ int ks_refine(ks_ctx *ctx, const ks_desc *desc, uint32_t num_series, uint64_t nu
 int ks_train_step(ks_ctx *ctx, ks_model *model, const float *features, uint64_t feature_rows, const ks_desc *desc,
                   const int32_t *labels, uint32_t num_series, uint32_t max_K, float lr, float *loss, void *stream);
 
+/* ------------------------------------------------------------ segmentation */
+
+/* Every level boundary of each series, by binary segmentation. The paper's
+ * test finds one change point per application, on a search interval narrowed
+ * until one boundary is isolated (workflow steps 2-4); here the test is
+ * applied to the whole series and then again to both sides [a, c) and [c, b)
+ * of every window whose split c is significant. Each window is a series of
+ * its own: eq. 2 with the window's own global minimum, every index a
+ * candidate, eq. 1 significance. A window of fewer than 2 rows, or a
+ * non-significant one, ends its branch; windows of depth d (0 = the whole
+ * series) are scanned while max_levels == 0 or d < max_levels.
+ *   desc        device, ks_desc[num_series] (aux_offset is ignored)
+ *   params      host, as for ks_scan_batch (max_K bounds every K)
+ *   max_levels  0 = until no window splits; 1 = the plain scan's split only
+ *   max_cp      capacity per series of cps (>= 1; K - 1 always suffices)
+ *   cps         device, ks_result[num_series * max_cp]: the boundaries of
+ *               series s at cps[s * max_cp ...], sorted by cp, where cp
+ *               counts rows from row 0 of the series; n = cp - a and m = b - cp
+ *               for the boundary's window [a, b); U, D, lambda, p and flags
+ *               are that window's; pad holds the window's depth
+ *   counts      device, uint32[num_series]: boundaries found for series s.
+ *               Above max_cp only max_cp of them are stored (which ones is
+ *               unspecified). 0xffffffff for a series whose descriptor
+ *               ks_scan_batch would flag KS_BAD_SHAPE or KS_OUT_OF_RANGE.
+ * The depths run breadth-first: one ks_scan_batch over all open windows per
+ * depth. Between depths the call reads back the next depth's window count
+ * and largest K, which synchronizes `stream` once per depth. The window
+ * workspace (num_series * max(1, max_K / 2) windows, 80 B each) grows on
+ * demand. KS_E_INVALID on a NULL pointer, max_cp == 0 or a bad parameter,
+ * KS_E_RANGE / KS_E_NOMEM as ks_scan_batch. */
+int ks_segment_batch(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, const ks_desc *desc,
+                     uint32_t num_series, const ks_params *params, uint32_t max_levels, uint32_t max_cp,
+                     ks_result *cps, uint32_t *counts, void *stream);
+
+#define KS_SEGMENT_BAD 0xffffffffu /* ks_segment_batch counts[s] of a malformed series */
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,9 @@ cites the passage it restates:
 * ``scan_series``    every index a candidate, the most significant one chosen,
                      eq. 1 significance, p-value as confidence (workflow step 4)
 * ``kolmogorov``     the asymptotic distribution behind eq. 1
+* ``segment``        every level boundary of one sweep: the single-change
+                     test applied again to both sides of each significant
+                     split (project-defined extension of workflow steps 2-4)
 * ``features``       per-row decile features of the learned proposal
                      (project-defined; minimum as in eq. 2)
 * ``cnn``            the proposal network, forward / backward / Adam in FP64
@@ -149,6 +152,40 @@ def refine(allU, K: int, proposal: int, confidence: float, w: int, tau: float, a
     out = result_fields(K, best, int(allU[best]), alpha)
     out["refined"] = refined
     return out
+
+
+def segment(r, alpha: float = 0.05, max_levels: int = 0) -> list[dict]:
+    """Binary segmentation of one [K][N] series into level boundaries.
+
+    The paper's test finds one change point per application, and its workflow
+    narrows the search interval until one boundary is isolated (workflow
+    steps 2-4). To report every boundary of one sweep, the test is applied to a
+    window of rows [a, b): the window is a series of its own (eq. 2 with the
+    window's own global minimum, every index a candidate, eq. 1 significance).
+    When the window's split c is significant, c is a boundary and both sides
+    [a, c) and [c, b) are tested in turn. A window of fewer than 2 rows, or a
+    non-significant one, ends its branch. Windows of depth d (0 = the whole
+    series) are tested only while max_levels == 0 or d < max_levels.
+
+    Returns one dict per boundary, sorted by position: cp (first row of the
+    higher side, counted from row 0 of the series), the window's fields n, m,
+    U, D, lambda, p (n = cp - a, m = b - cp) and its depth."""
+    r = _u32(r)
+    out = []
+    stack = [(0, r.shape[0], 0)]
+    while stack:
+        a, b, depth = stack.pop()
+        if b - a < 2 or (max_levels and depth >= max_levels):
+            continue
+        res = scan_series(r[a:b], alpha)
+        if not res["significant"]:
+            continue
+        c = a + int(res["cp"])
+        out.append({"cp": c, "n": int(res["n"]), "m": int(res["m"]), "U": int(res["U"]), "D": float(res["D"]),
+                    "lambda": float(res["lambda"]), "p": float(res["p"]), "depth": depth})
+        stack.append((a, c, depth + 1))
+        stack.append((c, b, depth + 1))
+    return sorted(out, key=lambda d: d["cp"])
 
 
 def scan_batch(samples, offsets, Ks, Ns, alpha: float = 0.05, threads: int | None = None,

@@ -38,6 +38,7 @@ KS_REFINED = 2
 KS_FALLBACK = 4
 KS_BAD_SHAPE = 8
 KS_OUT_OF_RANGE = 16
+KS_SEGMENT_BAD = 0xFFFFFFFF
 
 DESC_DTYPE = np.dtype([("offset", "<u8"), ("K", "<u4"), ("N", "<u4"), ("aux_offset", "<u8")])
 RESULT_DTYPE = np.dtype(
@@ -99,6 +100,7 @@ _SIGNATURES = {
     "ks_cnn_forward": ([_vp, _vp, _vp, _u64, _vp, _u32, _u32, _vp, _u64, _vp], ctypes.c_int),
     "ks_propose": ([_vp, _vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp, _vp, _u64, _vp], ctypes.c_int),
     "ks_refine": ([_vp, _vp, _u32, _u64, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "ks_segment_batch": ([_vp, _vp, _u64, _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp], ctypes.c_int),
     "ks_train_step": ([_vp, _vp, _vp, _u64, _vp, _vp, _u32, _u32, ctypes.c_float, _vp, _vp], ctypes.c_int),
 }
 
@@ -301,6 +303,19 @@ def ks_refine(ctx, desc, num_series: int, num_samples: int, proposal, confidence
                          _addr(proposal, 4 * num_series, "proposal"), _addr(confidence, 4 * num_series, "confidence"),
                          ctypes.byref(params), _addr(out, 48 * num_series, "out"), _stream(stream))
     _check(rc, "ks_refine")
+
+
+def ks_segment_batch(ctx, samples, desc, num_series: int, params: ks_params, max_levels: int, max_cp: int, cps,
+                     counts, stream=None, num_samples: int | None = None) -> None:
+    """Every level boundary of each series (binary segmentation). cps: ks_result[num_series * max_cp]
+    device buffer; counts: uint32[num_series] device buffer."""
+    if num_samples is None:
+        num_samples = samples.numel() * samples.element_size() // 4
+    rc = lib().ks_segment_batch(ctx, _addr(samples, 4 * num_samples, "samples"), num_samples,
+                                _addr(desc, 24 * num_series, "desc"), num_series, ctypes.byref(params), max_levels,
+                                max_cp, _addr(cps, 48 * num_series * max_cp, "cps"), _addr(counts, 4 * num_series, "counts"),
+                                _stream(stream))
+    _check(rc, "ks_segment_batch")
 
 
 def ks_train_step(ctx, model, features, desc, labels, num_series: int, max_K: int, lr: float, loss=None,

@@ -33,6 +33,7 @@ HIP_FLAGS = [
 KS_SOURCES = [
     "csrc/ks_api.hip",
     "csrc/ks_learn.hip",
+    "csrc/ks_segment.hip",
 ]
 
 TARGETS = {

@@ -333,6 +333,7 @@ int ks_ctx_destroy(ks_ctx* ctx) {
     }
     free_workspace(ctx);
     free_learn(ctx->learn);
+    free_seg(ctx->seg);
   }
   delete ctx;
   return KS_OK;

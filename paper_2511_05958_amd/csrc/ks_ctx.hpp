@@ -71,6 +71,17 @@ struct LearnBuffers {
   bool stamp_valid = false;
 };
 
+// Window workspace of the binary segmentation (ks_segment_batch), grown on demand.
+struct SegBuffers {
+  ks_desc* win[2] = {nullptr, nullptr};    // open windows of this / the next depth
+  uint32_t* wser[2] = {nullptr, nullptr};  // their series
+  uint32_t* wstart[2] = {nullptr, nullptr};  // their first row within the series
+  ks_result* res = nullptr;                // scan results of the open windows
+  uint32_t* ctr = nullptr;                 // device: next depth's window count, largest K
+  uint32_t* host_ctr = nullptr;            // pinned host copy of ctr
+  uint64_t cap = 0;                        // windows per buffer
+};
+
 int hip_fail(hipError_t e, const char* what);
 
 // Make the context's device current for the duration of a call.
@@ -102,6 +113,7 @@ inline int check_params(const ks_params* p) {
 }
 
 void free_learn(LearnBuffers& b);
+void free_seg(SegBuffers& b);
 
 }  // namespace ks_host
 
@@ -121,6 +133,7 @@ struct ks_ctx {
   std::map<std::tuple<int, int, uint32_t>, ks_host::GraphEntry> graphs;  // (mode, K class, grid)
   std::map<std::tuple<int, uint32_t>, ks_host::LaunchCfg> tuned;         // (K class, num_series)
   ks_host::LearnBuffers learn;
+  ks_host::SegBuffers seg;
 };
 
 struct ks_model {
