@@ -4,7 +4,10 @@
 
 One step = one ks_scan_batch call over the whole batch (eq. 2 reduction,
 K-S at every candidate, choice, significance and p-value for every series),
-with the samples already resident in HBM. Prints ONE JSON line.
+with the samples already resident in HBM. Prints ONE JSON line. Besides the
+headline it carries a "learned" leg (propose + exact refine with the trained
+network) and a "segment" leg (every level boundary by binary segmentation),
+each timed on the same batch.
 
 Workloads (seeded synthetic sweeps, see paper_2511_05958_amd.synth):
   c1  1 series, K=64, N=256            (launch-latency bound, not an HBM number)
@@ -130,6 +133,57 @@ def learned_leg(args, ctx, batch, samples, desc, out_plain, prm, stream, res_pla
     }
 
 
+def segment_leg(args, ctx, batch, samples, desc, prm, stream) -> dict:
+    """Every level boundary of each series (binary segmentation), timed per whole batch.
+    HBM bytes are counted exactly from the output: the samples once (depth 0), the 24-byte
+    row moments written at depth 0, and read again for every row of a later window (both
+    sides, of >= 2 rows, of every boundary's window)."""
+    import numpy as np
+    import torch
+
+    import paper_2511_05958_amd as P
+
+    n = batch.num_series
+    max_cp = 64
+    cps = torch.empty(n * max_cp * 48, dtype=torch.uint8, device="cuda")
+    counts = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    def step():
+        P.ks_segment_batch(ctx.handle, samples, desc, n, prm, 0, max_cp, cps, counts, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    c = counts.cpu().numpy().view(np.uint32)
+    v = cps.cpu().numpy().view(P.RESULT_DTYPE).reshape(n, max_cp)
+    Ns = batch.specs["N"].astype(np.int64)
+    rows = batch.specs["K"].astype(np.int64).copy()
+    depth = 0
+    for t in range(n):
+        k = min(int(c[t]), max_cp) if c[t] != P.KS_SEGMENT_BAD else 0
+        w = v[t][:k]
+        rows[t] += int(np.sum(np.where(w["n"] >= 2, w["n"], 0)) + np.sum(np.where(w["m"] >= 2, w["m"], 0)))
+        depth = max(depth, int(w["pad"].max()) + 1 if k else 0)
+    K0 = batch.specs["K"].astype(np.int64)
+    hbm = int(np.sum(4 * K0 * Ns) + 24 * np.sum(K0) + 24 * np.sum(rows - K0))
+    return {
+        "value": n / (wall_ms / 1e3),
+        "unit": "series/s",
+        "ms_per_step": wall_ms,
+        "boundaries_per_series": float(np.mean(np.where(c == P.KS_SEGMENT_BAD, 0, c))),
+        "truncated_series": int(np.count_nonzero((c != P.KS_SEGMENT_BAD) & (c > max_cp))),
+        "depths": depth + 1,
+        "window_rows": int(np.sum(rows)),
+        "hbm_bytes": hbm,
+        "hbm_GBps": hbm / (wall_ms / 1e3) / 1e9,
+    }
+
+
 # Sources of the scan kernels (plain path); their hash ties a recorded HBM
 # traffic figure to the code it was measured on.
 SCAN_SOURCES = ["include/ks.h", "paper_2511_05958_amd/csrc/ks_wave.hpp", "paper_2511_05958_amd/csrc/ks_scan.hpp",
@@ -203,6 +257,7 @@ def main() -> int:
     ap.add_argument("--model", default=os.path.join(MODEL_DIR, "proposal_r4.ckpt"),
                     help="trained proposal network; its .json report holds tau (learned mode is skipped if absent)")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-segment", action="store_true", help="skip the binary-segmentation leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -302,6 +357,8 @@ def main() -> int:
     }
     if not args.no_learned and os.path.exists(args.model) and batch.specs["N"].max() <= P.KS_FEATURE_MAX_N:
         line["learned"] = learned_leg(args, ctx, batch, samples, desc, out, prm, stream, res, n / (ms_per_step / 1e3))
+    if not args.no_segment:
+        line["segment"] = segment_leg(args, ctx, batch, samples, desc, prm, stream)
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))
         line["cpu_baseline"] = cpu_baseline(batch, samples, threads)

@@ -79,7 +79,9 @@ struct SegBuffers {
   ks_result* res = nullptr;                // scan results of the open windows
   uint32_t* ctr = nullptr;                 // device: next depth's window count, largest K
   uint32_t* host_ctr = nullptr;            // pinned host copy of ctr
+  ks::RowMom* rows = nullptr;              // per-row moments and minimum of depth 0 (s * max_K + i)
   uint64_t cap = 0;                        // windows per buffer
+  uint64_t cap_rows = 0;
 };
 
 int hip_fail(hipError_t e, const char* what);

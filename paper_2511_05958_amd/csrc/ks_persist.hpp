@@ -27,13 +27,6 @@ struct Item {
   uint16_t nchunks;
 };
 
-struct RowMom {
-  uint64_t s1;
-  uint64_t s2lo;
-  uint32_t s2hi;
-  uint32_t pad;
-};
-
 // Device workspace (owned by the context), passed by value.
 struct Workspace {
   uint32_t* hdr;       // [0] queue head, [1] number of items
@@ -165,7 +158,7 @@ __global__ __launch_bounds__(NT) void scan_persistent(const uint32_t* __restrict
     const uint32_t r0 = (uint32_t)item.chunk * rpc, r1 = min(K, r0 + rpc);
     RowMom* mom = ws.mom + ws.mom_base[s];
     const uint32_t mn = stream_rows(samples, d.offset, N, r0 + w, r1, S::W, lane,
-                                    [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h) {
+                                    [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t) {
                                       if (lane == 0) {
                                         mom[i].s1 = s1;
                                         mom[i].s2lo = s2;

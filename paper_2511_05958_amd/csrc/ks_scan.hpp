@@ -55,6 +55,16 @@ struct ScanSmem {
   uint32_t bestU[S::W], bestC[S::W];
 };
 
+// Moments of one row kept in device memory (split series of the persistent
+// plan; every row of a series under binary segmentation, with the row's
+// minimum in `pad`). 24 bytes.
+struct RowMom {
+  uint64_t s1;
+  uint64_t s2lo;
+  uint32_t s2hi;
+  uint32_t pad;
+};
+
 // ---------------------------------------------------------------- helpers
 
 __device__ __forceinline__ void acc_sample(uint32_t x, uint32_t& mn, uint64_t& s1, uint64_t& s2, uint32_t& s2h) {
@@ -208,14 +218,16 @@ __device__ __forceinline__ void acc_batch(const Batch& B, uint32_t& mn, uint64_t
 }
 
 // Streams rows rb, rb + step, ... < re of the series whose row i starts at
-// samples[off + i N]. For each row, emit(i, s1, s2lo, s2hi) receives the
-// wave-uniform totals (sum r, sum r^2). Returns this lane's running minimum.
-template <typename Emit>
+// samples[off + i N]. For each row, emit(i, s1, s2lo, s2hi, row_min) receives
+// the wave-uniform totals (sum r, sum r^2) and, when ROW_MIN, the row's
+// minimum (0xffffffff otherwise). Returns this lane's running minimum.
+template <bool ROW_MIN = false, typename Emit>
 __device__ __forceinline__ uint32_t stream_rows(const uint32_t* __restrict__ samples, uint64_t off, uint32_t N,
                                                 uint32_t rb, uint32_t re, uint32_t step, uint32_t lane,
                                                 Emit&& emit) {
   uint32_t mn = 0xffffffffu;
   if (rb >= re) return mn;
+  uint32_t rmn = 0xffffffffu;  // this row's lane minimum (ROW_MIN)
   uint32_t row = rb, b = 0;
   RowGeo g = row_geo(samples, off + (uint64_t)row * N, N);
   Batch cur, nxt;
@@ -232,10 +244,16 @@ __device__ __forceinline__ uint32_t stream_rows(const uint32_t* __restrict__ sam
     }
     const bool more = nrow < re;
     if (more) load_batch(nxt, samples, ng, nbb, lane);
-    acc_batch(cur, mn, s1, s2, s2h);
+    acc_batch(cur, ROW_MIN ? rmn : mn, s1, s2, s2h);
     if (b + 1 == g.nb) {
       wave_total_64_96(s1, s2, s2h);
-      emit(row, s1, s2, s2h);
+      uint32_t row_min = 0xffffffffu;
+      if constexpr (ROW_MIN) {
+        row_min = wave_min_u32(rmn);
+        mn = min(mn, row_min);
+        rmn = 0xffffffffu;
+      }
+      emit(row, s1, s2, s2h, row_min);
       s1 = 0;
       s2 = 0;
       s2h = 0;
@@ -271,7 +289,7 @@ __device__ uint32_t stream_moments(ScanSmem<KMAX, NT, RB>& sm, const uint32_t* _
   using S = ScanShape<KMAX, NT, RB>;
   const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
   const uint32_t mn = stream_rows(samples, off, N, w, K, S::W, lane,
-                                  [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h) {
+                                  [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t) {
                                     if (lane == 0) {
                                       sm.u.mom.s1[i] = s1;
                                       sm.u.mom.s2lo[i] = s2;

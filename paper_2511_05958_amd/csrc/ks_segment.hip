@@ -1,15 +1,18 @@
 // Binary segmentation over a batch: every level boundary of each series.
-// Depth by depth, all open windows of the batch are scanned by one
-// ks_scan_batch (each window a series of its own, with its own eq. 2
-// minimum); a split kernel records the significant splits and opens the two
-// sides of each as windows of the next depth; a final kernel sorts each
-// series' boundaries by position.
+// Depth 0 scans the whole series like ks_scan_batch and also keeps every
+// row's moments and minimum (24 B per row). A window [a, b) of a later depth
+// is a series of its own, but its eq. 2 keys need only its rows' sum r and
+// sum r^2 and the window's minimum (the least row minimum), so depths >= 1
+// read that workspace and never the samples. After each depth a split kernel
+// records the significant splits and opens both sides of each as windows of
+// the next depth; a final kernel sorts each series' boundaries by position.
 #include <hip/hip_runtime.h>
 
 #include <new>
 
 #include "ks.h"
 #include "ks_ctx.hpp"
+#include "ks_scan.hpp"
 #include "ks_wave.hpp"
 
 using namespace ks_host;
@@ -17,7 +20,7 @@ using namespace ks_host;
 namespace ks_host {
 
 void free_seg(SegBuffers& b) {
-  void* dev[] = {b.win[0], b.win[1], b.wser[0], b.wser[1], b.wstart[0], b.wstart[1], b.res, b.ctr};
+  void* dev[] = {b.win[0], b.win[1], b.wser[0], b.wser[1], b.wstart[0], b.wstart[1], b.res, b.ctr, b.rows};
   for (void* p : dev) (void)hipFree(p);
   if (b.host_ctr) (void)hipHostFree(b.host_ctr);
   b = SegBuffers{};
@@ -28,6 +31,88 @@ void free_seg(SegBuffers& b) {
 namespace {
 
 constexpr uint32_t kSegNT = 256;
+
+// Depth 0: the full scan of series blockIdx.x (as scan_kernel), also storing
+// each row's moments and minimum at rows[s * row_stride + i].
+template <int KMAX>
+__global__ __launch_bounds__(kNT) void seg_root_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
+                                                       const ks_desc* __restrict__ desc, uint32_t num_series,
+                                                       ks_params prm, uint32_t max_K, ks_result* __restrict__ out,
+                                                       ks::RowMom* __restrict__ rows, uint32_t row_stride) {
+  using S = ks::ScanShape<KMAX, kNT, kRB>;
+  __shared__ ks::ScanSmem<KMAX, kNT, kRB> sm;
+  const uint32_t s = blockIdx.x;
+  if (s >= num_series) return;
+  const ks_desc d = desc[s];
+  const uint32_t bad = ks::check_desc(d, num_samples, max_K);
+  if (bad) {
+    if (threadIdx.x == 0) ks::write_result(out + s, 0, 0, 0, 0, 0.0, 0.0, 1.0, bad);
+    return;
+  }
+  const uint32_t lane = ks::lane_id(), w = threadIdx.x / ks::kWave;
+  ks::RowMom* rm = rows + (uint64_t)s * row_stride;
+  const uint32_t mn = ks::stream_rows<true>(samples, d.offset, d.N, w, d.K, S::W, lane,
+                                            [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t rmin) {
+                                              if (lane == 0) {
+                                                sm.u.mom.s1[i] = s1;
+                                                sm.u.mom.s2lo[i] = s2;
+                                                sm.u.mom.s2hi[i] = s2h;
+                                                rm[i] = ks::RowMom{s1, s2, s2h, rmin};
+                                              }
+                                            });
+  const uint32_t gmin = ks::block_min_u32<kNT>(mn, sm.red);
+  ks::finish_series(sm, d.K, d.N, gmin, prm, out + s, nullptr);
+}
+
+// Depth >= 1: window t (series wser[t], rows wstart[t] .. + win[t].K) from the
+// stored row moments; its eq. 2 minimum is the least of its rows' minima.
+template <int KMAX>
+__global__ __launch_bounds__(kNT) void seg_window_kernel(const ks_desc* __restrict__ win, uint32_t n,
+                                                         const uint32_t* __restrict__ wser,
+                                                         const uint32_t* __restrict__ wstart, ks_params prm,
+                                                         const ks::RowMom* __restrict__ rows, uint32_t row_stride,
+                                                         ks_result* __restrict__ out) {
+  __shared__ ks::ScanSmem<KMAX, kNT, kRB> sm;
+  const uint32_t t = blockIdx.x;
+  if (t >= n) return;
+  const ks_desc d = win[t];
+  const uint32_t K = d.K;
+  if (K < 2 || K > (uint32_t)KMAX) {  // never opened by the split kernel
+    if (threadIdx.x == 0) ks::write_result(out + t, 0, 0, 0, 0, 0.0, 0.0, 1.0, KS_BAD_SHAPE);
+    return;
+  }
+  const ks::RowMom* rm = rows + (uint64_t)wser[t] * row_stride + wstart[t];
+  uint32_t mn = 0xffffffffu;
+  for (uint32_t i = threadIdx.x; i < K; i += kNT) {
+    const ks::RowMom r = rm[i];
+    sm.u.mom.s1[i] = r.s1;
+    sm.u.mom.s2lo[i] = r.s2lo;
+    sm.u.mom.s2hi[i] = r.s2hi;
+    mn = min(mn, r.pad);
+  }
+  const uint32_t gmin = ks::block_min_u32<kNT>(mn, sm.red);  // its barriers also publish the moments
+  ks::finish_series(sm, K, d.N, gmin, prm, out + t, nullptr);
+}
+
+template <template <int> class KERNEL, typename... Args>
+void launch_kc(int kc, uint32_t grid, hipStream_t st, Args... args) {
+  switch (kc) {
+    case 0: hipLaunchKernelGGL(KERNEL<64>::f, dim3(grid), dim3(kNT), 0, st, args...); break;
+    case 1: hipLaunchKernelGGL(KERNEL<128>::f, dim3(grid), dim3(kNT), 0, st, args...); break;
+    case 2: hipLaunchKernelGGL(KERNEL<256>::f, dim3(grid), dim3(kNT), 0, st, args...); break;
+    case 3: hipLaunchKernelGGL(KERNEL<512>::f, dim3(grid), dim3(kNT), 0, st, args...); break;
+    case 4: hipLaunchKernelGGL(KERNEL<1024>::f, dim3(grid), dim3(kNT), 0, st, args...); break;
+    default: hipLaunchKernelGGL(KERNEL<2048>::f, dim3(grid), dim3(kNT), 0, st, args...);
+  }
+}
+template <int KMAX>
+struct RootK {
+  static constexpr auto f = seg_root_kernel<KMAX>;
+};
+template <int KMAX>
+struct WindowK {
+  static constexpr auto f = seg_window_kernel<KMAX>;
+};
 
 // One thread per open window of depth `depth`. Window t is series wser[t]
 // (t itself at depth 0) starting at row wstart[t] (0 at depth 0).
@@ -104,14 +189,17 @@ bool alloc(T*& p, uint64_t n) {
   return hipMalloc(&p, sizeof(T) * (n ? n : 1)) == hipSuccess;
 }
 
-int ensure_seg(ks_ctx* c, uint64_t cap) {
+int ensure_seg(ks_ctx* c, uint64_t cap, uint64_t rows) {
   SegBuffers& b = c->seg;
-  if (cap <= b.cap) return KS_OK;
+  if (cap <= b.cap && rows <= b.cap_rows) return KS_OK;
+  if (cap < b.cap) cap = b.cap;
+  if (rows < b.cap_rows) rows = b.cap_rows;
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
   free_seg(b);
   bool ok = alloc(b.win[0], cap) && alloc(b.win[1], cap) && alloc(b.wser[0], cap) && alloc(b.wser[1], cap) &&
             alloc(b.wstart[0], cap) && alloc(b.wstart[1], cap) && alloc(b.res, cap) && alloc(b.ctr, 2) &&
+            alloc(b.rows, rows) &&
             hipHostMalloc(reinterpret_cast<void**>(&b.host_ctr), 2 * sizeof(uint32_t), hipHostMallocDefault) ==
                 hipSuccess;
   if (!ok) {
@@ -120,6 +208,7 @@ int ensure_seg(ks_ctx* c, uint64_t cap) {
     return KS_E_NOMEM;
   }
   b.cap = cap;
+  b.cap_rows = rows;
   return KS_OK;
 }
 
@@ -138,7 +227,7 @@ extern "C" int ks_segment_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t n
   if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
   // the windows of one depth are disjoint row ranges of >= 2 rows of their series
   const uint64_t cap = (uint64_t)num_series * (max_K / 2 > 1 ? max_K / 2 : 1);
-  if (int rc = ensure_seg(ctx, cap)) return rc;
+  if (int rc = ensure_seg(ctx, cap, (uint64_t)num_series * max_K)) return rc;
   SegBuffers& b = ctx->seg;
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * num_series, st);
@@ -150,9 +239,13 @@ extern "C" int ks_segment_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t n
   uint32_t roundK = max_K;
   int dst = 0;
   for (uint32_t depth = 0; n > 0 && (max_levels == 0 || depth < max_levels); ++depth) {
-    ks_params p = *params;
-    p.max_K = roundK;
-    if (int rc = ks_scan_batch(ctx, samples, num_samples, cur, (uint32_t)n, &p, b.res, nullptr, 0, stream)) return rc;
+    if (depth == 0)
+      launch_kc<RootK>(k_class(max_K), (uint32_t)n, st, samples, num_samples, desc, num_series, *params, max_K, b.res,
+                       b.rows, max_K);
+    else
+      launch_kc<WindowK>(k_class(roundK), (uint32_t)n, st, cur, (uint32_t)n, cser, cstart, *params,
+                         (const ks::RowMom*)b.rows, max_K, b.res);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "window scan launch");
     const int open_next = max_levels == 0 || depth + 1 < max_levels;
     if ((e = hipMemsetAsync(b.ctr, 0, 2 * sizeof(uint32_t), st)) != hipSuccess) return hip_fail(e, "window counter");
     hipLaunchKernelGGL(seg_split_kernel, dim3((uint32_t)((n + kSegNT - 1) / kSegNT)), dim3(kSegNT), 0, st, cur, b.res,
