@@ -78,7 +78,7 @@ __global__ __launch_bounds__(NTC) void conv_kernel(const uint16_t* __restrict__ 
   using S = ConvShape<CIN, COUT>;
   __shared__ __align__(16) uint16_t wl[COUT * S::WST];
   __shared__ __align__(16) uint16_t xl[S::XR * S::XST];
-  const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), w = wave_id();
   for (uint32_t q = tid; q < (uint32_t)(COUT * S::JP); q += NTC) {
     const uint32_t o = q / S::JP, j = q - o * S::JP;
     wl[o * S::WST + j] = j < (uint32_t)S::J ? Wg[o * S::J + j] : (uint16_t)0;
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(3))) void f
                                                             const float* __restrict__ b2, const float* __restrict__ b3,
                                                             float* __restrict__ logits) {
   __shared__ __align__(16) FusedSmem sm;
-  const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), w = wave_id();
   const uint32_t m = lane & 15u, kg = lane >> 4;
   const uint32_t o = w * 16 + m;
   // B operands of this wave's channels: W[o][32 q + 8 kg .. + 7]
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(NTC) void dw_kernel(const uint16_t* __restrict__ dY
   using S = DwShape<CIN, COUT>;
   __shared__ __align__(16) uint16_t yt[COUT * S::YST];
   __shared__ __align__(16) uint16_t xt[CIN * S::XST];
-  const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), w = wave_id();
   const uint32_t m = lane & 15u, kg = lane >> 4;
   f32x4 acc[S::PER_WAVE];
 #pragma unroll
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(NTC) void softmax_kernel(const float* __restrict__ 
                                                       uint16_t* __restrict__ dY, float* __restrict__ dYf, uint32_t w,
                                                       int32_t* __restrict__ proposal, float* __restrict__ conf) {
   const uint32_t lane = lane_id();
-  const uint32_t s = blockIdx.x * (NTC / kWave) + threadIdx.x / kWave;
+  const uint32_t s = blockIdx.x * (NTC / kWave) + wave_id();
   if (s >= num_series) return;
   const uint32_t K = Ks[s];
   const uint64_t base = (uint64_t)s * SR + 2;

@@ -315,7 +315,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 
   if (s >= num_series) return;
   const ks_desc d = desc[s];
   const uint32_t tid = threadIdx.x, lane = lane_id();
-  const uint32_t w = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const uint32_t w = wave_id();
   const bool bad = check_desc(d, num_samples, max_K) || d.N > KS_FEATURE_MAX_N;
   if ((bad ? 1u : feat_batches(d.N)) != (uint32_t)NB) return;
   if (bad) {

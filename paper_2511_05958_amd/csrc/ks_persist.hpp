@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kPlanNT) void plan_kernel(const ks_desc* __restrict
   __shared__ uint32_t hist[kBuckets];
   __shared__ uint32_t start[kBuckets];
   __shared__ uint64_t wsum[kPlanNT / kWave];
-  const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+  const uint32_t tid = threadIdx.x, lane = lane_id(), w = wave_id();
   for (uint32_t b = tid; b < (uint32_t)kBuckets; b += kPlanNT) hist[b] = 0;
   __syncthreads();
   const uint32_t per = (S + kPlanNT - 1) / kPlanNT;
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(NT) void scan_persistent(const uint32_t* __restrict
   // the plan writes at most kMaxChunks items per series
   const uint32_t cap = num_series <= 0xffffffffu / kMaxChunks ? num_series * kMaxChunks : 0xffffffffu;
   const uint32_t total = min(ws.hdr[1], cap);
-  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t lane = lane_id(), w = wave_id();
   for (;;) {
     // The barrier at the top of every iteration keeps the queue fetch below
     // from sitting next to any thread-0-only branch at the end of the

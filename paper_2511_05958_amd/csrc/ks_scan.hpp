@@ -271,7 +271,7 @@ __device__ __forceinline__ uint32_t stream_rows(const uint32_t* __restrict__ sam
 template <int NT>
 __device__ __forceinline__ uint32_t block_min_u32(uint32_t v, uint32_t* red) {
   constexpr int W = NT / kWave;
-  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t lane = lane_id(), w = wave_id();
   v = wave_min_u32(v);
   if (lane == 0) red[w] = v;
   __syncthreads();
@@ -287,7 +287,7 @@ template <int KMAX, int NT, int RB>
 __device__ uint32_t stream_moments(ScanSmem<KMAX, NT, RB>& sm, const uint32_t* __restrict__ samples, uint64_t off,
                                    uint32_t K, uint32_t N) {
   using S = ScanShape<KMAX, NT, RB>;
-  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t lane = lane_id(), w = wave_id();
   const uint32_t mn = stream_rows(samples, off, N, w, K, S::W, lane,
                                   [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t) {
                                     if (lane == 0) {
@@ -303,7 +303,7 @@ __device__ uint32_t stream_moments(ScanSmem<KMAX, NT, RB>& sm, const uint32_t* _
 template <int KMAX, int NT, int RB>
 __device__ int make_keys(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N, uint32_t gmin) {
   using S = ScanShape<KMAX, NT, RB>;
-  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t lane = lane_id(), w = wave_id();
   uint32_t o0 = 0, o1 = 0, o2 = 0;
   const u128 nm2 = (u128)((uint64_t)gmin * gmin) * N;
   const uint64_t twom = 2ull * gmin;
@@ -347,7 +347,7 @@ __device__ int make_keys(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N, uin
 template <int KMAX, int NT, int RB>
 __device__ bool sort_keys(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, int bits) {
   using S = ScanShape<KMAX, NT, RB>;
-  const uint32_t lane = lane_id(), w = threadIdx.x / kWave, tid = threadIdx.x;
+  const uint32_t lane = lane_id(), w = wave_id(), tid = threadIdx.x;
   const int passes = (bits + RB - 1) / RB;
   constexpr int C = (S::H + NT - 1) / NT;
   for (int p = 0; p < passes; ++p) {
@@ -425,7 +425,7 @@ __device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N
   if (c_hi > K - 1) c_hi = K - 1;
   if (c_lo < 1) c_lo = 1;
   using S = ScanShape<KMAX, NT, RB>;
-  const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t lane = lane_id(), w = wave_id();
   const int bits = make_keys(sm, K, N, gmin);
   const bool in_pong = sort_keys(sm, K, bits);
   uint32_t(*ks)[KMAX] = in_pong ? sm.u.pong.key : sm.key;

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kNT) void seg_root_kernel(const uint32_t* __restric
     if (threadIdx.x == 0) ks::write_result(out + s, 0, 0, 0, 0, 0.0, 0.0, 1.0, bad);
     return;
   }
-  const uint32_t lane = ks::lane_id(), w = threadIdx.x / ks::kWave;
+  const uint32_t lane = ks::lane_id(), w = ks::wave_id();
   ks::RowMom* rm = rows + (uint64_t)s * row_stride;
   const uint32_t mn = ks::stream_rows<true>(samples, d.offset, d.N, w, d.K, S::W, lane,
                                             [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t rmin) {
