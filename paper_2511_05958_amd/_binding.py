@@ -101,6 +101,7 @@ _SIGNATURES = {
     "ks_propose": ([_vp, _vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp, _vp, _u64, _vp], ctypes.c_int),
     "ks_refine": ([_vp, _vp, _u32, _u64, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "ks_segment_batch": ([_vp, _vp, _u64, _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp], ctypes.c_int),
+    "ks_probe_read": ([_vp, _u64, _u32, _u32, _vp, _vp], ctypes.c_int),
     "ks_train_step": ([_vp, _vp, _vp, _u64, _vp, _vp, _u32, _u32, ctypes.c_float, _vp, _vp], ctypes.c_int),
 }
 
@@ -316,6 +317,13 @@ def ks_segment_batch(ctx, samples, desc, num_series: int, params: ks_params, max
                                 max_cp, _addr(cps, 48 * num_series * max_cp, "cps"), _addr(counts, 4 * num_series, "counts"),
                                 _stream(stream))
     _check(rc, "ks_segment_batch")
+
+
+def ks_probe_read(words, grid: int, unroll: int, sink, stream=None) -> None:
+    """Read-bandwidth probe over a device buffer (measurement aid, include/ks_probe.h)."""
+    n = words.numel() * words.element_size() // 4
+    _check(lib().ks_probe_read(_addr(words, 4 * n, "words"), n, grid, unroll, _addr(sink, 4, "sink"), _stream(stream)),
+           "ks_probe_read")
 
 
 def ks_train_step(ctx, model, features, desc, labels, num_series: int, max_K: int, lr: float, loss=None,

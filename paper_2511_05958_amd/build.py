@@ -34,6 +34,7 @@ KS_SOURCES = [
     "csrc/ks_api.hip",
     "csrc/ks_learn.hip",
     "csrc/ks_segment.hip",
+    "csrc/ks_probe.hip",
 ]
 
 TARGETS = {
