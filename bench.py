@@ -31,6 +31,10 @@ import time
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_05958_amd", "models")
 
+# proposal networks trained on each workload's shapes (recipe 4 = recipe 2 under its own seed;
+# recipes 3 and 5 from series ids 2^20 on, disjoint from the benchmark batches)
+MODELS = {"c1": "proposal_r4.ckpt", "c2": "proposal_r4.ckpt", "c3": "proposal_r3.ckpt", "c5": "proposal_r5.ckpt"}
+
 WORKLOADS = {
     "c1": (1, None, "plain exact scan, 1 series x K=64 x N=256 (one 120->320 cycle change)"),
     "c2": (2, None, "plain exact scan, 4096 series x K=256 x N=1024 (1-4 planted levels)"),
@@ -298,12 +302,16 @@ def main() -> int:
                          "one workgroup per series, largest-first ordered grid, persistent queue (hipGraph), "
                          "persistent queue with direct launches")
     ap.add_argument("--chunk", type=int, default=1 << 20, help="split size of the persistent plan (bytes)")
-    ap.add_argument("--model", default=os.path.join(MODEL_DIR, "proposal_r4.ckpt"),
-                    help="trained proposal network; its .json report holds tau (learned mode is skipped if absent)")
+    ap.add_argument("--model", default=None,
+                    help="trained proposal network; its .json report holds tau (learned mode is skipped if absent). "
+                         "Default: the network trained on the workload's own shapes (series ids disjoint from the "
+                         "benchmark batch)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-segment", action="store_true", help="skip the binary-segmentation leg")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the measured read-ceiling probe")
     args = ap.parse_args()
+    if args.model is None:
+        args.model = os.path.join(MODEL_DIR, MODELS.get(args.workload, "proposal_r4.ckpt"))
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))

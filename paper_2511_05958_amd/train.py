@@ -1,9 +1,14 @@
 """Training and evaluation of the proposal network, on the GPU with the library's kernels.
 
     python -m paper_2511_05958_amd.train --series 200000 --epochs 10 --out model.ckpt
+    python -m paper_2511_05958_amd.train --recipe 5 --first-series 1048576 --series 40000 \
+        --val 4000 --chunk 1024 --out proposal_r5.ckpt
 
-Data: seeded synthetic sweeps of the training recipe (recipe 4: the shapes of
-recipe 2 under its own seed), generated on the device in chunks. Labels: the
+Data: seeded synthetic sweeps of a training recipe, generated on the device in
+chunks (only the per-row features stay resident). Recipe 4 is the shape of
+recipe 2 under its own seed. For the hard regime (recipe 5) the training
+series are recipe 5 series with ids from --first-series on, disjoint from the
+benchmark batch's ids 0..8191 (the generator is keyed by series id). Labels: the
 exact scan (ks_scan_batch): the change point of every significant series, -1
 (skipped by the loss) otherwise. Inputs: ks_features. Steps: ks_train_step
 (softmax cross-entropy, Adam). The last `val` series are held out; on them the
@@ -176,12 +181,15 @@ def main() -> int:
     ap.add_argument("--target", type=float, default=0.995)
     ap.add_argument("--out", default="proposal.ckpt")
     ap.add_argument("--report", default=None)
+    ap.add_argument("--recipe", type=int, default=4, help="training recipe (4: recipe-2 shapes, own seed; 5: hard regime)")
+    ap.add_argument("--first-series", type=int, default=0, help="first series id of the training data")
+    ap.add_argument("--chunk", type=int, default=2048, help="series generated per device chunk")
     args = ap.parse_args()
     ctx = P.Context(0)
     model = P.Model(ctx, seed=args.seed)
     t0 = time.perf_counter()
     ntrain = args.series - args.val
-    feats, desc, labels, _ = generate(ctx.handle, 4, ntrain, 0)
+    feats, desc, labels, _ = generate(ctx.handle, args.recipe, ntrain, args.first_series, chunk=args.chunk)
     print(f"generated {ntrain} training series ({int((labels >= 1).sum())} significant) in "
           f"{time.perf_counter() - t0:.1f} s", flush=True)
     t1 = time.perf_counter()
@@ -190,10 +198,11 @@ def main() -> int:
     train_s = time.perf_counter() - t1
     del feats
     torch.cuda.empty_cache()
-    ev = evaluate(ctx.handle, model.handle, 4, args.val, ntrain)
+    ev = evaluate(ctx.handle, model.handle, args.recipe, args.val, args.first_series + ntrain, chunk=args.chunk)
     tau, agr, fb = calibrate_tau(ev["agree"], ev["confidence"], args.target)
     P.ks_model_save(model.handle, args.out)
-    rep = {"train_series": ntrain, "val_series": args.val, "epochs": args.epochs, "batch": args.batch,
+    rep = {"recipe": args.recipe, "first_series": args.first_series, "train_series": ntrain, "val_series": args.val,
+           "epochs": args.epochs, "batch": args.batch,
            "lr": args.lr, "losses": losses, "train_seconds": train_s,
            "val_agreement_no_fallback": float(ev["agree"].mean()),
            "val_agreement_trivial_no_fallback": float(ev["agree_trivial"].mean()),
