@@ -6,8 +6,9 @@ One step = one ks_scan_batch call over the whole batch (eq. 2 reduction,
 K-S at every candidate, choice, significance and p-value for every series),
 with the samples already resident in HBM. Prints ONE JSON line. Besides the
 headline it carries a "learned" leg (propose + exact refine with the trained
-network) and a "segment" leg (every level boundary by binary segmentation),
-each timed on the same batch.
+network), a "segment" leg (every level boundary by binary segmentation) and a
+"row_stats" leg (per-row mean, std, min, p50, p95, max), each timed on the
+same batch.
 
 Workloads (seeded synthetic sweeps, see paper_2511_05958_amd.synth):
   c1  1 series, K=64, N=256            (launch-latency bound, not an HBM number)
@@ -195,9 +196,38 @@ def segment_leg(args, ctx, batch, samples, desc, prm, stream) -> dict:
     }
 
 
+def stats_leg(args, batch, samples, desc, prm, ctx, stream) -> dict:
+    """Per-row latency statistics (ks_stats_batch) of the whole batch: one read of the samples."""
+    import numpy as np
+    import torch
+
+    import paper_2511_05958_amd as P
+
+    rows = int(batch.specs["K"].astype(np.int64).sum())
+    out = torch.empty(rows * 32, dtype=torch.uint8, device="cuda")
+
+    def step():
+        P.ks_stats_batch(ctx.handle, samples, desc, batch.num_series, prm.max_K, out, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(args.steps):
+        step()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    return {"value": rows / (ms / 1e3), "unit": "rows/s", "ms_per_step": ms,
+            "series_per_s": batch.num_series / (ms / 1e3), "hbm_GBps": (batch.sample_bytes + 32 * rows) / (ms / 1e3) / 1e9}
+
+
 # Sources of the scan kernels (plain path); their hash ties a recorded HBM
 # traffic figure to the code it was measured on.
-SCAN_SOURCES = ["include/ks.h", "paper_2511_05958_amd/csrc/ks_wave.hpp", "paper_2511_05958_amd/csrc/ks_scan.hpp",
+# (The ABI structs of include/ks.h are pinned separately: static_asserts on their sizes and the
+# ctypes layouts' itemsize checks.)
+SCAN_SOURCES = ["paper_2511_05958_amd/csrc/ks_wave.hpp", "paper_2511_05958_amd/csrc/ks_scan.hpp",
                 "paper_2511_05958_amd/csrc/ks_persist.hpp", "paper_2511_05958_amd/csrc/ks_ctx.hpp",
                 "paper_2511_05958_amd/csrc/ks_api.hip"]
 TRAFFIC_FILE = os.path.join("profiles", "hbm_traffic.txt")
@@ -309,6 +339,7 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-segment", action="store_true", help="skip the binary-segmentation leg")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the measured read-ceiling probe")
+    ap.add_argument("--no-stats", action="store_true", help="skip the per-row statistics leg")
     args = ap.parse_args()
     if args.model is None:
         args.model = os.path.join(MODEL_DIR, MODELS.get(args.workload, "proposal_r4.ckpt"))
@@ -421,6 +452,8 @@ def main() -> int:
         line["learned"] = learned_leg(args, ctx, batch, samples, desc, out, prm, stream, res, n / (ms_per_step / 1e3))
     if not args.no_segment:
         line["segment"] = segment_leg(args, ctx, batch, samples, desc, prm, stream)
+    if not args.no_stats and batch.specs["N"].max() <= P.KS_FEATURE_MAX_N:
+        line["row_stats"] = stats_leg(args, batch, samples, desc, prm, ctx, stream)
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))
         line["cpu_baseline"] = cpu_baseline(batch, samples, threads)

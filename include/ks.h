@@ -331,6 +331,36 @@ int ks_segment_batch(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples,
 
 #define KS_SEGMENT_BAD 0xffffffffu /* ks_segment_batch counts[s] of a malformed series */
 
+/* ---------------------------------------------------- per-row statistics */
+
+/* Latency statistics of one row (one array size's N measurements): the
+ * average as the main result, with p50, p95 and the standard deviation
+ * beside it (Section "Load Latency benchmarks"), plus the minimum and
+ * maximum. 32 bytes.
+ *   mean     (sum r) / N: one FP64 division of the exact integer sum
+ *   std      population standard deviation: num = N sum r^2 - (sum r)^2
+ *            exact in 128 bits, rounded once to FP64, divided by N^2 in
+ *            FP64, FP64 square root
+ *   min, p50, p95, max   x_(floor(q (N - 1))) of the row sorted ascending,
+ *            for q = 0, 0.5, 0.95, 1 */
+typedef struct ks_row_stats {
+  double mean;
+  double std;
+  uint32_t min, p50, p95, max;
+} ks_row_stats;
+
+/* Statistics of every row of every series, in one read of the samples.
+ *   desc      device, ks_desc[num_series]; series s writes its rows to
+ *             out[aux_offset + i], i < K, when aux_offset + K <= out_rows
+ *   max_K     upper bound on K (0 = KS_MAX_K), as for ks_scan_batch
+ *   out       device, ks_row_stats[out_rows]
+ * A series that ks_scan_batch would flag (KS_BAD_SHAPE, KS_OUT_OF_RANGE), or
+ * with N > KS_FEATURE_MAX_N, writes mean = std = NaN and zeros for its rows.
+ * KS_E_INVALID on a NULL pointer, KS_E_RANGE on max_K outside [2,
+ * KS_MAX_K]. */
+int ks_stats_batch(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, const ks_desc *desc,
+                   uint32_t num_series, uint32_t max_K, ks_row_stats *out, uint64_t out_rows, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,9 @@ cites the passage it restates:
 * ``scan_series``    every index a candidate, the most significant one chosen,
                      eq. 1 significance, p-value as confidence (workflow step 4)
 * ``kolmogorov``     the asymptotic distribution behind eq. 1
+* ``row_stats``      per-row latency statistics: the average, p50, p95 and
+                     standard deviation (Section "Load Latency benchmarks"),
+                     with minimum and maximum
 * ``segment``        every level boundary of one sweep: the single-change
                      test applied again to both sides of each significant
                      split (project-defined extension of workflow steps 2-4)
@@ -28,6 +31,7 @@ cites the passage it restates:
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from pathlib import Path
 
@@ -151,6 +155,38 @@ def refine(allU, K: int, proposal: int, confidence: float, w: int, tau: float, a
             best = c
     out = result_fields(K, best, int(allU[best]), alpha)
     out["refined"] = refined
+    return out
+
+
+ROW_STATS_DTYPE = np.dtype([("mean", "<f8"), ("std", "<f8"), ("min", "<u4"), ("p50", "<u4"), ("p95", "<u4"),
+                            ("max", "<u4")])
+
+
+def row_stats(r) -> np.ndarray:
+    """Per-row latency statistics of a [K][N] series: the average as the main
+    result, with p50, p95 and the standard deviation (Section "Load Latency
+    benchmarks"), and the minimum and maximum. With exact integer sums
+    s1 = sum r and s2 = sum r^2 of a row:
+        mean = s1 / N, one correctly rounded division;
+        std  = sqrt(float(N s2 - s1^2) / (N N)), the exact numerator rounded
+               once to double, then double division and square root;
+        p50, p95 = x_(floor(q (N - 1))) of the row sorted ascending, q = 0.5,
+               0.95 (floor in exact integer arithmetic); min, max likewise.
+    Plain Python integers, one row at a time."""
+    r = _u32(r)
+    K, N = r.shape
+    out = np.zeros(K, ROW_STATS_DTYPE)
+    for i in range(K):
+        row = [int(v) for v in r[i]]
+        s1 = sum(row)
+        s2 = sum(v * v for v in row)
+        srt = sorted(row)
+        out[i]["mean"] = s1 / N
+        out[i]["std"] = math.sqrt(float(N * s2 - s1 * s1) / float(N * N))
+        out[i]["min"] = srt[0]
+        out[i]["p50"] = srt[(N - 1) // 2]
+        out[i]["p95"] = srt[(95 * (N - 1)) // 100]
+        out[i]["max"] = srt[-1]
     return out
 
 

@@ -45,7 +45,9 @@ RESULT_DTYPE = np.dtype(
     [("cp", "<u4"), ("n", "<u4"), ("m", "<u4"), ("U", "<u4"), ("D", "<f8"), ("lambda", "<f8"),
      ("p", "<f8"), ("flags", "<u4"), ("pad", "<u4")]
 )
-assert DESC_DTYPE.itemsize == 24 and RESULT_DTYPE.itemsize == 48
+ROW_STATS_DTYPE = np.dtype([("mean", "<f8"), ("std", "<f8"), ("min", "<u4"), ("p50", "<u4"), ("p95", "<u4"),
+                            ("max", "<u4")])
+assert DESC_DTYPE.itemsize == 24 and RESULT_DTYPE.itemsize == 48 and ROW_STATS_DTYPE.itemsize == 32
 
 
 class ks_params(ctypes.Structure):
@@ -102,6 +104,7 @@ _SIGNATURES = {
     "ks_refine": ([_vp, _vp, _u32, _u64, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "ks_segment_batch": ([_vp, _vp, _u64, _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp], ctypes.c_int),
     "ks_probe_read": ([_vp, _u64, _u32, _u32, _vp, _vp], ctypes.c_int),
+    "ks_stats_batch": ([_vp, _vp, _u64, _vp, _u32, _u32, _vp, _u64, _vp], ctypes.c_int),
     "ks_train_step": ([_vp, _vp, _vp, _u64, _vp, _vp, _u32, _u32, ctypes.c_float, _vp, _vp], ctypes.c_int),
 }
 
@@ -317,6 +320,18 @@ def ks_segment_batch(ctx, samples, desc, num_series: int, params: ks_params, max
                                 max_cp, _addr(cps, 48 * num_series * max_cp, "cps"), _addr(counts, 4 * num_series, "counts"),
                                 _stream(stream))
     _check(rc, "ks_segment_batch")
+
+
+def ks_stats_batch(ctx, samples, desc, num_series: int, max_K: int, out, stream=None,
+                   num_samples: int | None = None) -> None:
+    """Per-row latency statistics (mean, std, min, p50, p95, max) of every series; out: a device
+    buffer of ROW_STATS_DTYPE records, series s at rows aux_offset .. aux_offset + K."""
+    if num_samples is None:
+        num_samples = samples.numel() * samples.element_size() // 4
+    rc = lib().ks_stats_batch(ctx, _addr(samples, 4 * num_samples, "samples"), num_samples,
+                              _addr(desc, 24 * num_series, "desc"), num_series, max_K, _addr(out, None, "out"),
+                              _nelem(out, 32), _stream(stream))
+    _check(rc, "ks_stats_batch")
 
 
 def ks_probe_read(words, grid: int, unroll: int, sink, stream=None) -> None:

@@ -35,6 +35,7 @@ KS_SOURCES = [
     "csrc/ks_learn.hip",
     "csrc/ks_segment.hip",
     "csrc/ks_probe.hip",
+    "csrc/ks_stats.hip",
 ]
 
 TARGETS = {

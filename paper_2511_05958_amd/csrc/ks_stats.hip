@@ -1,0 +1,104 @@
+// Per-row latency statistics (ks_stats_batch): the average as the main result,
+// with p50, p95, standard deviation, minimum and maximum beside it, for every
+// row of every series in one read of the samples. One wave per row, the row
+// in registers; the two percentiles come from the same multi-rank radix
+// select as the learned path's deciles.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "ks.h"
+#include "ks_ctx.hpp"
+#include "ks_scan.hpp"
+#include "ks_select.hpp"
+
+static_assert(sizeof(ks_desc) == 24 && sizeof(ks_result) == 48 && sizeof(ks_params) == 32 &&
+                  sizeof(ks_row_stats) == 32,
+              "ABI struct sizes");
+
+using namespace ks_host;
+
+namespace {
+
+// p50 and p95: x_(floor(q (N - 1))) for q = 0.5, 0.95.
+struct StatRanks {
+  static constexpr uint32_t kCount = 2;
+  __device__ static uint32_t rank(uint32_t j, uint32_t N) {
+    return j == 0 ? (N - 1) / 2u : (uint32_t)((95ull * (N - 1)) / 100u);
+  }
+};
+
+typedef unsigned __int128 u128;
+
+// u128 -> double, rounded to nearest even once: the top 64 significant bits
+// with a sticky bit for everything below, converted, then scaled exactly.
+__device__ double u128_to_double(u128 v) {
+  const uint64_t hi = (uint64_t)(v >> 64);
+  if (hi == 0) return (double)(uint64_t)v;
+  const int sh = 64 - __clzll(hi);  // bits above the low 64
+  const uint64_t top = (uint64_t)(v >> sh);
+  const bool sticky = (v & (((u128)1 << sh) - 1)) != 0;
+  return ldexp((double)(top | (uint64_t)sticky), sh);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void row_stats_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
+                                                        const ks_desc* __restrict__ desc, uint32_t num_series,
+                                                        uint32_t max_K, ks_row_stats* __restrict__ out,
+                                                        uint64_t out_rows) {
+  constexpr int W = 4;
+  __shared__ ks::SelLds sel[W];
+  const uint32_t s = blockIdx.x;
+  if (s >= num_series) return;
+  const ks_desc d = desc[s];
+  const uint32_t lane = ks::lane_id(), w = ks::wave_id();
+  const bool bad = ks::check_desc(d, num_samples, max_K) || d.N > KS_FEATURE_MAX_N;
+  if ((bad ? 1u : ks::feat_batches(d.N)) != (uint32_t)NB) return;
+  const bool fits = d.aux_offset <= out_rows && (uint64_t)d.K <= out_rows - d.aux_offset;
+  if (!fits) return;
+  ks_row_stats* o = out + d.aux_offset;
+  if (bad) {
+    for (uint32_t i = threadIdx.x; i < d.K; i += 256) o[i] = ks_row_stats{NAN, NAN, 0u, 0u, 0u, 0u};
+    return;
+  }
+  const uint32_t K = d.K, N = d.N;
+  ks::SelLds& L = sel[w];
+  ks::Batch cur[NB];
+  for (uint32_t i = w; i < K; i += W) {
+    ks::load_row<NB>(cur, samples, d.offset + (uint64_t)i * N, N, lane);
+    uint64_t s1, s2;
+    uint32_t s2h, rmax, sel_x;
+    const uint32_t rmin = ks::row_pass<NB, StatRanks>(L, cur, N, lane, s1, s2, s2h, rmax, sel_x);
+    const uint32_t p95 = (uint32_t)__builtin_amdgcn_readlane((int)sel_x, 1);
+    if (lane == 0) {
+      const u128 S2 = ((u128)s2h << 64) | s2;
+      const u128 num = (u128)N * S2 - (u128)s1 * s1;  // >= 0 (Cauchy-Schwarz), < 2^113
+      const double nn = (double)N * (double)N;
+      o[i] = ks_row_stats{(double)s1 / (double)N, sqrt(u128_to_double(num) / nn), rmin, sel_x, p95, rmax};
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" int ks_stats_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, const ks_desc* desc,
+                              uint32_t num_series, uint32_t max_K, ks_row_stats* out, uint64_t out_rows, void* stream) {
+  if (!ctx) return KS_E_INVALID;
+  if (max_K == 0) max_K = KS_MAX_K;
+  if (max_K < 2 || max_K > KS_MAX_K) return KS_E_RANGE;
+  if (num_series == 0) return KS_OK;
+  if (!samples || !desc || !out) return KS_E_INVALID;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  // one launch per row length class (1, 2 or 4 load batches per row); each
+  // workgroup whose series belongs to another class returns at once
+  hipLaunchKernelGGL(row_stats_kernel<1>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
+                     max_K, out, out_rows);
+  hipLaunchKernelGGL(row_stats_kernel<2>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
+                     max_K, out, out_rows);
+  hipLaunchKernelGGL(row_stats_kernel<4>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
+                     max_K, out, out_rows);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? KS_OK : hip_fail(e, "row stats launch");
+}
