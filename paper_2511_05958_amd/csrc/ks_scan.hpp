@@ -82,6 +82,17 @@ __device__ __forceinline__ uint32_t key_digit(uint32_t k0, uint32_t k1, uint32_t
   return (uint32_t)((((uint64_t)b << 32) | a) >> o) & mask;
 }
 
+// |a - b| for unsigned a, b in one v_sad_u32 (register arithmetic only).
+__device__ __forceinline__ uint32_t abs_diff(uint32_t a, uint32_t b) {
+  uint32_t d;
+  asm("v_sad_u32 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
+  return d;
+}
+
+// Largest KMAX whose walk keeps its per-position terms in registers (3 VGPRs
+// per 64-position chunk).
+constexpr int kIncrWalkKMax = 512;
+
 // Does candidate a beat candidate b? lambda^2 = U^2 / (c (K - c) K); compared
 // exactly by cross-multiplying (U^2 <= 2^40, c (K - c) <= 2^20).
 __device__ __forceinline__ bool more_significant(uint32_t Ua, uint32_t a, uint32_t Ub, uint32_t b, uint32_t K) {
@@ -444,9 +455,56 @@ __device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N
   }
   __syncthreads();
 
+  uint32_t bU = 0, bC = 0;
+  if constexpr (KMAX <= kIncrWalkKMax) {
+    // lattice walk, incremental: wave w takes the contiguous candidates
+    // [ca, cb]. With A(p) = K i_c(p) and B(p) = c (p + 1) per sorted position
+    // p, U_c = max over tie-group ends of |A - B|. From c to c + 1 only row c
+    // joins the lower side: A += K at positions >= pos(c), B += p + 1.
+    constexpr int R = KMAX / kWave;  // 64-position chunks
+    uint16_t* pos = in_pong ? sm.idx : sm.u.pong.idx;  // the sort's free index buffer
+    for (uint32_t p = threadIdx.x; p < K; p += NT) pos[is[p]] = (uint16_t)p;
+    const uint32_t n = c_hi >= c_lo ? c_hi - c_lo + 1 : 0;
+    const uint32_t len = (n + S::W - 1) / S::W;
+    const uint32_t ca = c_lo + w * len, cb = min(c_hi, ca + len - 1);
+    uint32_t A[R], B[R], T[R];
+    uint32_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const uint32_t p = k * kWave + lane;
+      const uint32_t row = p < K ? (uint32_t)is[p] : 0xffffffffu;
+      const bool lt = row < ca;
+      const uint64_t msk = ballot(lt);
+      A[k] = K * (carry + mbcnt(msk) + (lt ? 1u : 0u));
+      B[k] = ca * (p + 1);
+      // chunks past K hold an earlier series' tie words: positions >= K never count
+      T[k] = (p < K && ((sm.tie[k] >> lane) & 1ull)) ? 0xffffffffu : 0u;
+      carry += (uint32_t)__popcll(msk);
+    }
+    __syncthreads();  // pos[] complete
+    for (uint32_t c = ca; c <= cb && ca <= c_hi; ++c) {
+      if (c > ca) {
+        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)pos[c - 1]);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          const uint32_t p = k * kWave + lane;
+          A[k] += p >= q ? K : 0u;
+          B[k] += p + 1;
+        }
+      }
+      uint32_t mx = 0;
+#pragma unroll
+      for (int k = 0; k < R; ++k) mx = max(mx, abs_diff(A[k], B[k]) & T[k]);
+      const uint32_t Uc = wave_max_u32(mx);
+      if (allU && lane == 0) allU[c] = Uc;
+      if (bC == 0 || more_significant(Uc, c, bU, bC, K)) {
+        bU = Uc;
+        bC = c;
+      }
+    }
+  } else {
   // lattice walk over the candidates c = 1 + w, 1 + w + W, ...
   const uint32_t nch = (K + kWave - 1) / kWave;
-  uint32_t bU = 0, bC = 0;
   for (uint32_t c = c_lo + w; c <= c_hi; c += S::W) {
     uint32_t carry = 0, mx = 0;
     for (uint32_t k = 0; k < nch; ++k) {
@@ -466,6 +524,7 @@ __device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N
       bU = Uc;
       bC = c;
     }
+  }
   }
   if (lane == 0) {
     sm.bestU[w] = bU;
