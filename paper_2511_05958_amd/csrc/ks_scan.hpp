@@ -8,12 +8,14 @@
 //   3. LDS LSD radix sort of the K (Q_i, i) pairs, RB-bit digits, only as
 //      many passes as Q's bit length needs; mark the ends of equal-key groups;
 //   4. lattice walk: for each candidate c, U_c = max over group ends p of
-//      |K i_c(p) - c (p + 1)| with i_c(p) = #{q <= p : row(q) < c}, by
-//      ballot / mbcnt prefix counts over 64 sorted positions at a time
-//      (this is max |i m - j n| with j = p + 1 - i, the D numerator);
+//      |K i_c(p) - c (p + 1)| with i_c(p) = #{q <= p : row(q) < c}, one
+//      candidate per lane stepping through the sorted positions (this is
+//      max |i m - j n| with j = p + 1 - i, the D numerator);
 //   5. exact argmax of U_c^2 / (c (K - c)), eq. 1 significance, FP64
 //      Kolmogorov p-value of the winner only.
 #pragma once
+
+#include <type_traits>
 
 #include "ks.h"
 #include "ks_wave.hpp"
@@ -53,6 +55,7 @@ struct ScanSmem {
   uint16_t hist[S::H];
   uint32_t red[S::W * 4];
   uint32_t bestU[S::W], bestC[S::W];
+  uint32_t partU[S::W * kWave];  // per-lane partial U_c of walks split over positions
 };
 
 // Moments of one row kept in device memory (split series of the persistent
@@ -81,17 +84,6 @@ __device__ __forceinline__ uint32_t key_digit(uint32_t k0, uint32_t k1, uint32_t
   const uint32_t b = w == 0 ? k1 : (w == 1 ? k2 : 0u);
   return (uint32_t)((((uint64_t)b << 32) | a) >> o) & mask;
 }
-
-// |a - b| for unsigned a, b in one v_sad_u32 (register arithmetic only).
-__device__ __forceinline__ uint32_t abs_diff(uint32_t a, uint32_t b) {
-  uint32_t d;
-  asm("v_sad_u32 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
-  return d;
-}
-
-// Largest KMAX whose walk keeps its per-position terms in registers (3 VGPRs
-// per 64-position chunk).
-constexpr int kIncrWalkKMax = 512;
 
 // Does candidate a beat candidate b? lambda^2 = U^2 / (c (K - c) K); compared
 // exactly by cross-multiplying (U^2 <= 2^40, c (K - c) <= 2^20).
@@ -426,6 +418,229 @@ __device__ bool sort_keys(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, int bits) {
   return (passes & 1) != 0;
 }
 
+// ---------------------------------------------------------------- lattice walk
+//
+// The candidate sits on the lane: lane l of slot j holds c = c_lo + 64 j + l
+// and D_c(p) = K i_c(p) - c (p + 1), i_c(p) = #{q <= p : row(q) < c}, for the
+// sorted positions p in order. Each step adds K - c where the row at p is
+// below c and -c otherwise (the row is the same for every lane, read once per
+// four positions); U_c = max over tie-group ends of |D_c(p)| is kept as a
+// running max and min of D. No cross-lane work until the argmax at the end.
+
+// |D| <= c (K - c) <= K^2 / 4 < 2^21: int32 holds every step.
+template <int G>
+__device__ __forceinline__ void walk_step(uint32_t r, const uint32_t (&c)[G], const int32_t (&up)[G],
+                                          const int32_t (&dn)[G], int32_t (&D)[G]) {
+#pragma unroll
+  for (int g = 0; g < G; ++g) D[g] += r < c[g] ? up[g] : dn[g];
+}
+
+// Positions [pa, pb) of one pass. TIES = false: every position ends a group
+// (no two Q equal), so the walk takes eight positions per broadcast read with
+// no per-position test; TIES = true reads the group-end bits.
+template <int KMAX, int G, bool TIES>
+__device__ __forceinline__ void walk_positions(const uint16_t* __restrict__ is, const uint64_t* __restrict__ tie,
+                                               uint32_t pa, uint32_t pb, uint32_t K, const uint32_t (&c)[G],
+                                               int32_t (&D)[G], int32_t (&mx)[G], int32_t (&mn)[G]) {
+  int32_t up[G], dn[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    up[g] = (int32_t)K - (int32_t)c[g];
+    dn[g] = -(int32_t)c[g];
+  }
+  uint32_t p = pa;
+  if constexpr (!TIES) {
+    // pa is a multiple of 8: two 8-byte aligned broadcast reads per group,
+    // the next group's issued before this one's arithmetic (the address
+    // clamped inside the KMAX-entry array; a clamped read goes unused)
+    uint2 na = make_uint2(0u, 0u), nb = make_uint2(0u, 0u);
+    if (p + 8 <= pb) {
+      na = *reinterpret_cast<const uint2*>(is + p);
+      nb = *reinterpret_cast<const uint2*>(is + p + 4);
+    }
+    for (; p + 8 <= pb; p += 8) {
+      const uint2 ra = na, rb = nb;
+      const uint32_t pn = min(p + 8, KMAX - 8u);
+      na = *reinterpret_cast<const uint2*>(is + pn);
+      nb = *reinterpret_cast<const uint2*>(is + pn + 4);
+      const uint32_t w[4] = {(uint32_t)__builtin_amdgcn_readfirstlane((int)ra.x),
+                             (uint32_t)__builtin_amdgcn_readfirstlane((int)ra.y),
+                             (uint32_t)__builtin_amdgcn_readfirstlane((int)rb.x),
+                             (uint32_t)__builtin_amdgcn_readfirstlane((int)rb.y)};
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        int32_t v[8];
+        int32_t x = D[g];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint32_t r = (j & 1) ? (w[j >> 1] >> 16) : (w[j >> 1] & 0xffffu);
+          x += r < c[g] ? up[g] : dn[g];
+          v[j] = x;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          mx[g] = max(max(mx[g], v[j]), v[j + 1]);
+          mn[g] = min(min(mn[g], v[j]), v[j + 1]);
+        }
+        D[g] = x;
+      }
+    }
+  }
+  // the rest one position at a time (TIES: all of [pa, pb))
+  for (; p < pb; ++p) {
+    const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)is[p]);
+    walk_step<G>(r, c, up, dn, D);
+    bool end = true;
+    if constexpr (TIES) {
+      const uint64_t t = tie[p >> 6] >> (p & 63);
+      end = (__builtin_amdgcn_readfirstlane((int)(uint32_t)t) & 1) != 0;
+    }
+    if (end) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        mx[g] = max(mx[g], D[g]);
+        mn[g] = min(mn[g], D[g]);
+      }
+    }
+  }
+}
+
+// Best (U, c) of a wave: exact lambda order, ties to the smaller c; c = 0 is
+// "no candidate". A float key U^2 / (c (K - c)) (relative error under 2^-21:
+// U^2 rounded once, an rcp within 1 ulp, one rounded product) finds the
+// maximum by a DPP max; every lane within 16 ulps of it (2^-20 relative or
+// more) is then compared exactly, one lane at a time.
+__device__ __forceinline__ void wave_best(uint32_t& U, uint32_t& c, uint32_t K) {
+  uint32_t key = 0;
+  if (c != 0) {
+    const float u = (float)U;  // U <= K^2 / 4 < 2^24: exact
+    const float f = (u * u) * __builtin_amdgcn_rcpf((float)(c * (K - c)));
+    key = __float_as_uint(f) + 1u;  // f >= 0: bits order as f; 0 stays "none"
+  }
+  const uint32_t kmax = wave_max_u32(key);
+  uint64_t cand = ballot(key != 0 && key + 16u >= kmax);
+  uint32_t bu = 0, bc = 0;
+  while (cand) {
+    const int l = __builtin_ctzll(cand);
+    cand &= cand - 1;
+    const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)U, l);
+    const uint32_t cc = (uint32_t)__builtin_amdgcn_readlane((int)c, l);
+    if (bc == 0 || more_significant(u, cc, bu, bc, K)) {
+      bu = u;
+      bc = cc;
+    }
+  }
+  U = bu;
+  c = bc;
+}
+
+// Walk of one pass over G slots (wave-uniform) on positions [pa, pb); with
+// pa > 0, D starts from K i_c(pa - 1) - c pa, the count taken from pos[]
+// (the sorted position of every row). Returns the partial U per slot.
+template <int KMAX, int G>
+__device__ __forceinline__ void walk_pass(const uint16_t* __restrict__ is, const uint16_t* __restrict__ pos,
+                                          const uint64_t* __restrict__ tie, bool ties, uint32_t K, uint32_t pa,
+                                          uint32_t pb, const uint32_t (&c)[G], uint32_t (&U)[G]) {
+  const uint32_t lane = lane_id();
+  int32_t D[G], mx[G], mn[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    D[g] = 0;
+    mx[g] = 0;  // D = 0 at p = K - 1 (always a group end): 0 bounds U from below
+    mn[g] = 0;
+  }
+  if (pa > 0) {
+    uint32_t cnt[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) cnt[g] = 0;
+    for (uint32_t j = 0; j * kWave < K; ++j) {
+      const uint32_t r = j * kWave + lane;
+      const uint64_t bal = ballot(r < K && pos[r] < pa);
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int32_t x = (int32_t)c[g] - (int32_t)(j * kWave);  // rows of this chunk below c
+        const uint64_t m = x >= kWave ? ~0ull : (x <= 0 ? 0ull : ((1ull << x) - 1ull));
+        cnt[g] += (uint32_t)__popcll(bal & m);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) D[g] = (int32_t)(K * cnt[g]) - (int32_t)(c[g] * pa);
+  }
+  if (ties)
+    walk_positions<KMAX, G, true>(is, tie, pa, pb, K, c, D, mx, mn);
+  else
+    walk_positions<KMAX, G, false>(is, tie, pa, pb, K, c, D, mx, mn);
+#pragma unroll
+  for (int g = 0; g < G; ++g) U[g] = (uint32_t)max(mx[g], -mn[g]);
+}
+
+// Candidates c_lo..c_hi over 64-lane slots. With at least one slot per wave,
+// wave w walks every position for slots w, w + W, ... (up to kMaxG at a time);
+// with fewer slots than waves, the waves of a slot split the positions (shares
+// of a multiple of 8) and their partial maxima meet in LDS. ties: some two Q
+// are equal. (bU, bC) is the wave's best (bC = 0: none).
+template <int KMAX, int NT, int RB>
+__device__ void walk_splits(ScanSmem<KMAX, NT, RB>& sm, const uint16_t* __restrict__ is, uint16_t* __restrict__ pos,
+                            bool ties, uint32_t K, uint32_t c_lo, uint32_t c_hi, uint32_t* __restrict__ allU,
+                            uint32_t& bU, uint32_t& bC) {
+  using S = ScanShape<KMAX, NT, RB>;
+  constexpr int W = S::W;
+  constexpr int kMaxG = S::CH / W < 1 ? 1 : (S::CH / W > 4 ? 4 : S::CH / W);
+  const uint32_t lane = lane_id(), w = wave_id();
+  const uint32_t n = c_hi >= c_lo ? c_hi - c_lo + 1 : 0;
+  const uint32_t ns = (n + kWave - 1) / kWave;
+  bU = 0;
+  bC = 0;
+  auto consider = [&](uint32_t c, uint32_t U) {
+    if (c > c_hi) return;
+    if (allU) allU[c] = U;
+    if (bC == 0 || more_significant(U, c, bU, bC, K)) {
+      bU = U;
+      bC = c;
+    }
+  };
+  if (ns >= (uint32_t)W) {
+    const uint32_t mine = ns / W + (w < ns % W ? 1u : 0u);  // slots w, w + W, ...
+    for (uint32_t j0 = 0; j0 < mine;) {
+      const uint32_t take = min(mine - j0, (uint32_t)kMaxG);
+      auto run = [&](auto gtag) {
+        constexpr int G = decltype(gtag)::value;
+        uint32_t c[G], U[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) c[g] = c_lo + (w + (j0 + g) * W) * kWave + lane;
+        walk_pass<KMAX, G>(is, nullptr, sm.tie, ties, K, 0, K, c, U);
+#pragma unroll
+        for (int g = 0; g < G; ++g) consider(c[g], U[g]);
+      };
+      if (take == 4) run(std::integral_constant<int, (kMaxG >= 4 ? 4 : 1)>{});
+      else if (take == 3) run(std::integral_constant<int, (kMaxG >= 3 ? 3 : 1)>{});
+      else if (take == 2) run(std::integral_constant<int, (kMaxG >= 2 ? 2 : 1)>{});
+      else run(std::integral_constant<int, 1>{});
+      j0 += take;
+    }
+  } else if (ns > 0) {
+    // fewer slots than waves: P waves per slot, each a 4-aligned share of the positions
+    const uint32_t P = W / ns;
+    const uint32_t slot = w / P, part = w % P;
+    for (uint32_t p = threadIdx.x; p < K; p += NT) pos[is[p]] = (uint16_t)p;
+    __syncthreads();
+    const uint32_t len = ((K + P - 1) / P + 7u) & ~7u;
+    uint32_t c[1], U[1] = {0};
+    c[0] = c_lo + slot * kWave + lane;
+    if (slot < ns) {
+      const uint32_t pa = min(K, part * len), pb = min(K, pa + len);
+      walk_pass<KMAX, 1>(is, pos, sm.tie, ties, K, pa, pb, c, U);
+    }
+    sm.partU[w * kWave + lane] = U[0];
+    __syncthreads();
+    if (slot < ns && part == 0) {
+      for (uint32_t q = 1; q < P; ++q) U[0] = max(U[0], sm.partU[(w + q) * kWave + lane]);
+      consider(c[0], U[0]);
+    }
+  }
+  wave_best(bU, bC, K);
+}
+
 // Phases 4-5 for one series already holding moments in LDS: the walk and the
 // choice cover the candidates c_lo..c_hi (inclusive; 1..K-1 for the full
 // scan); extra_flags are or-ed into the result flags.
@@ -443,6 +658,7 @@ __device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N
   const uint16_t* is = in_pong ? sm.u.pong.idx : sm.idx;
 
   // ends of equal-key groups
+  bool any_tie = false;
   for (uint32_t p0 = w * kWave; p0 < K; p0 += NT) {
     const uint32_t p = p0 + lane;
     bool end = false;
@@ -452,80 +668,16 @@ __device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N
       end = true;
     const uint64_t m = ballot(end);
     if (lane == 0) sm.tie[p0 / kWave] = m;
+    any_tie |= m != ballot(p < K);
   }
+  if (lane == 0) sm.red[w] = any_tie ? 1u : 0u;
   __syncthreads();
+  bool ties = false;
+#pragma unroll
+  for (int v = 0; v < S::W; ++v) ties |= sm.red[v] != 0;
 
   uint32_t bU = 0, bC = 0;
-  if constexpr (KMAX <= kIncrWalkKMax) {
-    // lattice walk, incremental: wave w takes the contiguous candidates
-    // [ca, cb]. With A(p) = K i_c(p) and B(p) = c (p + 1) per sorted position
-    // p, U_c = max over tie-group ends of |A - B|. From c to c + 1 only row c
-    // joins the lower side: A += K at positions >= pos(c), B += p + 1.
-    constexpr int R = KMAX / kWave;  // 64-position chunks
-    uint16_t* pos = in_pong ? sm.idx : sm.u.pong.idx;  // the sort's free index buffer
-    for (uint32_t p = threadIdx.x; p < K; p += NT) pos[is[p]] = (uint16_t)p;
-    const uint32_t n = c_hi >= c_lo ? c_hi - c_lo + 1 : 0;
-    const uint32_t len = (n + S::W - 1) / S::W;
-    const uint32_t ca = c_lo + w * len, cb = min(c_hi, ca + len - 1);
-    uint32_t A[R], B[R], T[R];
-    uint32_t carry = 0;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const uint32_t p = k * kWave + lane;
-      const uint32_t row = p < K ? (uint32_t)is[p] : 0xffffffffu;
-      const bool lt = row < ca;
-      const uint64_t msk = ballot(lt);
-      A[k] = K * (carry + mbcnt(msk) + (lt ? 1u : 0u));
-      B[k] = ca * (p + 1);
-      // chunks past K hold an earlier series' tie words: positions >= K never count
-      T[k] = (p < K && ((sm.tie[k] >> lane) & 1ull)) ? 0xffffffffu : 0u;
-      carry += (uint32_t)__popcll(msk);
-    }
-    __syncthreads();  // pos[] complete
-    for (uint32_t c = ca; c <= cb && ca <= c_hi; ++c) {
-      if (c > ca) {
-        const uint32_t q = (uint32_t)__builtin_amdgcn_readfirstlane((int)pos[c - 1]);
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-          const uint32_t p = k * kWave + lane;
-          A[k] += p >= q ? K : 0u;
-          B[k] += p + 1;
-        }
-      }
-      uint32_t mx = 0;
-#pragma unroll
-      for (int k = 0; k < R; ++k) mx = max(mx, abs_diff(A[k], B[k]) & T[k]);
-      const uint32_t Uc = wave_max_u32(mx);
-      if (allU && lane == 0) allU[c] = Uc;
-      if (bC == 0 || more_significant(Uc, c, bU, bC, K)) {
-        bU = Uc;
-        bC = c;
-      }
-    }
-  } else {
-  // lattice walk over the candidates c = 1 + w, 1 + w + W, ...
-  const uint32_t nch = (K + kWave - 1) / kWave;
-  for (uint32_t c = c_lo + w; c <= c_hi; c += S::W) {
-    uint32_t carry = 0, mx = 0;
-    for (uint32_t k = 0; k < nch; ++k) {
-      const uint32_t p = k * kWave + lane;
-      const uint32_t row = p < K ? (uint32_t)is[p] : 0xffffffffu;
-      const bool lt = row < c;
-      const uint64_t msk = ballot(lt);
-      const uint32_t incl = carry + mbcnt(msk) + (lt ? 1u : 0u);
-      const int32_t f = (int32_t)(K * incl) - (int32_t)(c * (p + 1));
-      const uint32_t af = (uint32_t)(f < 0 ? -f : f);
-      if ((sm.tie[k] >> lane) & 1ull) mx = max(mx, af);
-      carry += (uint32_t)__popcll(msk);
-    }
-    const uint32_t Uc = wave_max_u32(mx);
-    if (allU && lane == 0) allU[c] = Uc;
-    if (bC == 0 || more_significant(Uc, c, bU, bC, K)) {
-      bU = Uc;
-      bC = c;
-    }
-  }
-  }
+  walk_splits(sm, is, in_pong ? sm.idx : sm.u.pong.idx, ties, K, c_lo, c_hi, allU, bU, bC);
   if (lane == 0) {
     sm.bestU[w] = bU;
     sm.bestC[w] = bC;
