@@ -220,14 +220,141 @@ __device__ __forceinline__ void acc_batch(const Batch& B, uint32_t& mn, uint64_t
   if (B.m & 16u) acc_sample(B.x, mn, s1, s2, s2h);
 }
 
+// ---- short rows: several rows per wave
+//
+// A row of N <= 16 GL samples fits one batch of a GL-lane group (GL = 16: a
+// DPP row of the wave; GL = 32: two), so a wave streams 64 / GL rows per step
+// and each row's sums need only in-group DPP steps.
+
+// Group sums: afterwards every lane of a 16-lane DPP row holds its row's
+// total (GL = 16), or the upper row of each pair holds the pair's (GL = 32).
+template <int GL>
+__device__ __forceinline__ void group_total_64_96(uint64_t& s1, uint64_t& s2, uint32_t& s2h) {
+  dpp_add64<kDppXor1>(s1);
+  dpp_add96<kDppXor1>(s2, s2h);
+  dpp_add64<kDppXor2>(s1);
+  dpp_add96<kDppXor2>(s2, s2h);
+  dpp_add64<kDppHalfMirror>(s1);
+  dpp_add96<kDppHalfMirror>(s2, s2h);
+  dpp_add64<kDppMirror>(s1);
+  dpp_add96<kDppMirror>(s2, s2h);
+  if constexpr (GL == 32) {
+    dpp_add64<kDppBcast15, 0xA>(s1);
+    dpp_add96<kDppBcast15, 0xA>(s2, s2h);
+  }
+}
+
+template <int GL>
+__device__ __forceinline__ uint32_t group_min_u32(uint32_t v) {
+  v = min(v, dpp<kDppXor1>(v));
+  v = min(v, dpp<kDppXor2>(v));
+  v = min(v, dpp<kDppHalfMirror>(v));
+  v = min(v, dpp<kDppMirror>(v));
+  if constexpr (GL == 32)
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kDppBcast15, 0xA, 0xF, false));
+  return v;
+}
+
+// The group's row (when `valid`): the unaligned head in lanes 0.., the
+// aligned body as 16-byte quads gl, gl + GL, ... (nqu of them at most, a
+// wave-uniform bound), the tail in lanes GL / 2.. ; the rest zero.
+template <int GL>
+__device__ __forceinline__ void load_group(Batch& B, const uint32_t* __restrict__ samples, uint64_t e0, uint32_t N,
+                                           bool valid, uint32_t gl, uint32_t nqu) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) B.q[u] = u32x4{0u, 0u, 0u, 0u};
+  B.x = 0;
+  if (valid) {
+    const uint32_t a = (uint32_t)(((uintptr_t)(samples + e0) >> 2) & 3u);
+    const uint32_t head = a ? min(4u - a, N) : 0u;
+    const uint32_t nq = (N - head) >> 2, tail = (N - head) & 3u;
+    const u32x4* body = reinterpret_cast<const u32x4*>(samples + e0 + head);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if ((uint32_t)u < nqu && gl + u * GL < nq) {
+        B.q[u] = __builtin_nontemporal_load(body + gl + u * GL);
+        m |= 1u << u;
+      }
+    }
+    if (gl < head) {
+      B.x = __builtin_nontemporal_load(samples + e0 + gl);
+      m |= 16u;
+    } else if (gl >= GL / 2 && gl - GL / 2 < tail) {
+      B.x = __builtin_nontemporal_load(samples + e0 + head + 4ull * nq + (gl - GL / 2));
+      m |= 16u;
+    }
+  }
+  B.m = m;
+}
+
+template <int GL, bool ROW_MIN, typename Emit>
+__device__ __forceinline__ uint32_t stream_rows_grouped(const uint32_t* __restrict__ samples, uint64_t off,
+                                                        uint32_t N, uint32_t rb, uint32_t re, uint32_t step,
+                                                        uint32_t lane, Emit&& emit) {
+  constexpr uint32_t RPW = kWave / GL;  // rows per wave step
+  uint32_t mn = 0xffffffffu;
+  if (rb >= re) return mn;
+  const uint32_t g = lane / GL, gl = lane % GL;
+  const uint32_t nqu = min(4u, ((N >> 2) + GL - 1) / GL);
+  // step i, group g: row rb + (i RPW + g) step. One batch of registers: the
+  // next rows' loads go out once this step's samples are summed, ahead of
+  // the group reductions and the emits.
+  uint32_t base = rb;
+  Batch cur;
+  {
+    const uint32_t row = base + g * step;
+    load_group<GL>(cur, samples, off + (uint64_t)row * N, N, row < re, gl, nqu);
+  }
+  for (;;) {
+    uint64_t s1 = 0, s2 = 0;
+    uint32_t s2h = 0, rmn = 0xffffffffu;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if ((uint32_t)u < nqu && (cur.m & (1u << u))) acc_quad(cur.q[u], ROW_MIN ? rmn : mn, s1, s2, s2h);
+    if (cur.m & 16u) acc_sample(cur.x, ROW_MIN ? rmn : mn, s1, s2, s2h);
+    const uint32_t nbase = base + RPW * step;
+    const bool more = nbase < re;
+    if (more) {
+      const uint32_t row = nbase + g * step;
+      load_group<GL>(cur, samples, off + (uint64_t)row * N, N, row < re, gl, nqu);
+    }
+    group_total_64_96<GL>(s1, s2, s2h);
+    if constexpr (ROW_MIN) {
+      rmn = group_min_u32<GL>(rmn);
+      mn = min(mn, rmn);
+    }
+#pragma unroll
+    for (uint32_t gg = 0; gg < RPW; ++gg) {
+      const uint32_t row = base + gg * step;
+      if (row < re) {
+        const int src = (int)(gg * GL + GL - 1);
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)s1, src);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(s1 >> 32), src);
+        const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)s2, src);
+        const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(s2 >> 32), src);
+        const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)s2h, src);
+        const uint32_t rm = ROW_MIN ? (uint32_t)__builtin_amdgcn_readlane((int)rmn, src) : 0xffffffffu;
+        emit(row, ((uint64_t)b << 32) | a, ((uint64_t)d << 32) | c, h, rm);
+      }
+    }
+    if (!more) break;
+    base = nbase;
+  }
+  return mn;
+}
+
 // Streams rows rb, rb + step, ... < re of the series whose row i starts at
 // samples[off + i N]. For each row, emit(i, s1, s2lo, s2hi, row_min) receives
 // the wave-uniform totals (sum r, sum r^2) and, when ROW_MIN, the row's
-// minimum (0xffffffff otherwise). Returns this lane's running minimum.
+// minimum (0xffffffff otherwise). Returns this lane's running minimum. Rows
+// of up to 512 samples go several to a wave (stream_rows_grouped).
 template <bool ROW_MIN = false, typename Emit>
 __device__ __forceinline__ uint32_t stream_rows(const uint32_t* __restrict__ samples, uint64_t off, uint32_t N,
                                                 uint32_t rb, uint32_t re, uint32_t step, uint32_t lane,
                                                 Emit&& emit) {
+  if (N <= 16u * 16u) return stream_rows_grouped<16, ROW_MIN>(samples, off, N, rb, re, step, lane, emit);
+  if (N <= 16u * 32u) return stream_rows_grouped<32, ROW_MIN>(samples, off, N, rb, re, step, lane, emit);
   uint32_t mn = 0xffffffffu;
   if (rb >= re) return mn;
   uint32_t rmn = 0xffffffffu;  // this row's lane minimum (ROW_MIN)

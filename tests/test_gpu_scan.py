@@ -124,19 +124,23 @@ def test_parity_recipe1_many_draws(ctx):
 
 @pytest.mark.parametrize("launch", [LAUNCHES[0], LAUNCHES[1], LAUNCHES[5]], ids=["grid", "ordered", "split16k-direct"])
 def test_parity_all_K_variants_and_alpha(ctx, launch):
-    # one launch per LDS variant, K at the top of each class
+    # one launch per LDS variant, K at the top of each class; N on both sides of
+    # the row-group limits (a 16- or 32-lane group per row up to 256 / 512
+    # samples), series starts shifted by 0-3 elements off 16-byte alignment
     rng = np.random.default_rng(7)
     for K in (64, 128, 256, 512, 1024, 2048):
-        Ns = [1, 3, 64, 257]
+        Ns = [1, 3, 64, 255, 256, 257, 511, 512, 513]
         parts, offs, off = [], [], 0
-        for N in Ns:
+        for j, N in enumerate(Ns):
+            shift = j % 4
+            parts.append(np.zeros(shift, np.uint32))
             r = rng.integers(100, 140, (K, N), dtype=np.uint32)
             r[K // 3:] += 25
             parts.append(r.ravel())
-            pad = (-r.size) % 64
+            pad = (-(shift + r.size)) % 64
             parts.append(np.zeros(pad, np.uint32))
-            offs.append(off)
-            off += r.size + pad
+            offs.append(off + shift)
+            off += shift + r.size + pad
         x = np.concatenate(parts)
         d = P.make_desc(offs, [K] * len(Ns), Ns)
         for alpha in (0.05, 0.001):
