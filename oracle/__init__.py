@@ -26,6 +26,9 @@ cites the passage it restates:
                      (project-defined; minimum as in eq. 2)
 * ``cnn``            the proposal network, forward / backward / Adam in FP64
                      with BF16 operand rounding (project-defined)
+* ``check_sweep``, ``align_fraction``, ``line_size`` (in ``sweep.py``): the
+                     workflow's outlier check and interval widening, the L2
+                     segment alignment, the cache-line-size heuristic
 """
 
 from __future__ import annotations
@@ -246,3 +249,8 @@ def scan_batch(samples, offsets, Ks, Ns, alpha: float = 0.05, threads: int | Non
     _load().oracle_scan_batch(samples.ctypes.data, offsets.ctypes.data, Ks.ctypes.data, Ns.ctypes.data,
                               num, alpha, res.ctypes.data, None, None, threads)
     return res
+
+
+from .sweep import (CHECK_DISTURBED, CHECK_DTYPE, CHECK_EDGE_HIGH, CHECK_EDGE_LOW, CHECK_NO_CHANGE,  # noqa: E402
+                    LINE_DTYPE, LINE_INCONCLUSIVE, LINE_NO_INCREASE, LINE_NO_MAX_LIKE, align_fraction,
+                    check_sweep, line_size, lower_median)
