@@ -8,7 +8,9 @@ with the samples already resident in HBM. Prints ONE JSON line. Besides the
 headline it carries a "learned" leg (propose + exact refine with the trained
 network), a "segment" leg (every level boundary by binary segmentation) and a
 "row_stats" leg (per-row mean, std, min, p50, p95, max), each timed on the
-same batch.
+same batch, a "check" leg (workflow step 3's outlier check and widening, and the
+L2 segment alignment, on the same detections) and a "line_size" leg (the
+cache-line-size scoring on its own synthetic experiments).
 
 Workloads (seeded synthetic sweeps, see paper_2511_05958_amd.synth):
   c1  1 series, K=64, N=256            (launch-latency bound, not an HBM number)
@@ -220,7 +222,95 @@ def stats_leg(args, batch, samples, desc, prm, ctx, stream) -> dict:
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / args.steps
     return {"value": rows / (ms / 1e3), "unit": "rows/s", "ms_per_step": ms,
-            "series_per_s": batch.num_series / (ms / 1e3), "hbm_GBps": (batch.sample_bytes + 32 * rows) / (ms / 1e3) / 1e9}
+            "series_per_s": batch.num_series / (ms / 1e3),
+            "hbm_GBps": (batch.sample_bytes + 32 * rows) / (ms / 1e3) / 1e9}, out
+
+
+def timed(args, stream, fn) -> float:
+    """Average ms of fn over args.steps calls after args.warmup, HIP events on `stream`."""
+    import torch
+
+    for _ in range(args.warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(args.steps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / args.steps
+
+
+def check_leg(args, ctx, batch, desc, prm, out_plain, stats, stats_ms, stream) -> dict:
+    """Workflow step 3 on every sweep (ks_check_batch: outlier check and widening from the
+    detection and the per-step p50), and the L2 segment alignment (ks_align_batch) of each
+    significant sweep's boundary size against a 32 MiB reported L2 (8 XCDs x 4 MiB). The
+    chain after the scan is ks_stats_batch (timed in row_stats) + ks_check_batch."""
+    import numpy as np
+    import torch
+
+    import paper_2511_05958_amd as P
+
+    n = batch.num_series
+    out = torch.empty(n * 32, dtype=torch.uint8, device="cuda")
+    ms = timed(args, stream, lambda: P.ks_check_batch(ctx.handle, desc, n, prm.max_K, out_plain, stats, out,
+                                                       stream=stream))
+    chk = out.cpu().numpy().view(P.CHECK_DTYPE)
+    fl = chk["flags"]
+    res = P.results_to_numpy(out_plain)
+    sig = np.nonzero(res["flags"] & P.KS_SIGNIFICANT)[0]
+    # boundary size of a significant sweep: footprint 1 KiB * 2^(16 cp / (K - 1)) (the sweep's rows)
+    K = batch.specs["K"][sig].astype(np.float64)
+    S_ = np.rint(1024.0 * np.exp2(16.0 * res["cp"][sig] / (K - 1))).astype(np.int64)
+    m = len(sig)
+    Sd = torch.tensor(S_, device="cuda")
+    Td = torch.full((m,), 32 << 20, dtype=torch.int64, device="cuda")
+    seg = torch.empty(m, dtype=torch.int32, device="cuda")
+    al = torch.empty(m, dtype=torch.float64, device="cuda")
+    di = torch.empty(m, dtype=torch.float64, device="cuda")
+    ams = timed(args, stream, lambda: P.ks_align_batch(Sd, Td, m, seg, al, di, stream=stream)) if m else 0.0
+    return {"value": n / ((stats_ms + ms) / 1e3), "unit": "sweeps/s", "ms_per_step": stats_ms + ms,
+            "check_kernel_ms": ms, "per_step_stats_ms": stats_ms,
+            "edge_low": int(np.count_nonzero(fl & P.KS_CHECK_EDGE_LOW)),
+            "edge_high": int(np.count_nonzero(fl & P.KS_CHECK_EDGE_HIGH)),
+            "no_change": int(np.count_nonzero(fl & P.KS_CHECK_NO_CHANGE)),
+            "disturbed": int(np.count_nonzero(fl & P.KS_CHECK_DISTURBED)),
+            "invalid": int(np.count_nonzero(fl & P.KS_CHECK_INVALID)),
+            "align": {"items": m, "ms": ams}}
+
+
+def line_leg(args, ctx, stream, num_exp: int = 1024, J: int = 16, A: int = 32, N: int = 256) -> dict:
+    """Cache-line-size scoring: num_exp synthetic experiments (J strides x A array sizes x N
+    latencies, synth.line_experiments) through ks_stats_batch (p50 per stride and size) and
+    ks_line_batch, timed as one step; accuracy = share of experiments whose line size is
+    the planted one."""
+    import numpy as np
+    import torch
+
+    import paper_2511_05958_amd as P
+    from paper_2511_05958_amd import synth as S
+
+    x, strides, planted = S.line_experiments(num_exp, J, A, N)
+    K = J * A
+    d = P.make_desc(np.arange(num_exp, dtype=np.int64) * K * N, [K] * num_exp, [N] * num_exp)
+    xd, dd = P.to_device(x), P.to_device(d)
+    st = torch.tensor(strides.view(np.int32), device="cuda")
+    stats = torch.empty(num_exp * K * 32, dtype=torch.uint8, device="cuda")
+    out = torch.empty(num_exp * 24, dtype=torch.uint8, device="cuda")
+
+    def step():
+        P.ks_stats_batch(ctx.handle, xd, dd, num_exp, K, stats, stream=stream)
+        P.ks_line_batch(ctx.handle, dd, num_exp, stats, J, st, out, stream=stream)
+
+    ms = timed(args, stream, step)
+    lms = timed(args, stream, lambda: P.ks_line_batch(ctx.handle, dd, num_exp, stats, J, st, out, stream=stream))
+    r = out.cpu().numpy().view(P.LINE_DTYPE)
+    return {"value": num_exp / (ms / 1e3), "unit": "experiments/s", "ms_per_step": ms, "line_kernel_ms": lms,
+            "experiments": num_exp, "strides": J, "sizes": A, "samples": N, "sample_bytes": int(x.nbytes),
+            "hbm_GBps": x.nbytes / (ms / 1e3) / 1e9,
+            "planted_found": float(np.mean(r["line"] == planted)),
+            "inconclusive": int(np.count_nonzero(r["flags"] & (P.KS_LINE_INCONCLUSIVE | P.KS_LINE_INVALID)))}
 
 
 # Sources of the scan kernels (plain path); their hash ties a recorded HBM
@@ -340,6 +430,8 @@ def main() -> int:
     ap.add_argument("--no-segment", action="store_true", help="skip the binary-segmentation leg")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the measured read-ceiling probe")
     ap.add_argument("--no-stats", action="store_true", help="skip the per-row statistics leg")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the workflow-check legs (outlier check, L2 alignment, cache-line size)")
     args = ap.parse_args()
     if args.model is None:
         args.model = os.path.join(MODEL_DIR, MODELS.get(args.workload, "proposal_r4.ckpt"))
@@ -453,7 +545,13 @@ def main() -> int:
     if not args.no_segment:
         line["segment"] = segment_leg(args, ctx, batch, samples, desc, prm, stream)
     if not args.no_stats and batch.specs["N"].max() <= P.KS_FEATURE_MAX_N:
-        line["row_stats"] = stats_leg(args, batch, samples, desc, prm, ctx, stream)
+        line["row_stats"], stats_out = stats_leg(args, batch, samples, desc, prm, ctx, stream)
+        if not args.no_check:
+            line["check"] = check_leg(args, ctx, batch, desc, prm, out, stats_out, line["row_stats"]["ms_per_step"],
+                                      stream)
+            del stats_out
+    if not args.no_check:
+        line["line_size"] = line_leg(args, ctx, stream)
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))
         line["cpu_baseline"] = cpu_baseline(batch, samples, threads)

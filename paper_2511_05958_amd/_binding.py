@@ -49,6 +49,21 @@ ROW_STATS_DTYPE = np.dtype([("mean", "<f8"), ("std", "<f8"), ("min", "<u4"), ("p
                             ("max", "<u4")])
 assert DESC_DTYPE.itemsize == 24 and RESULT_DTYPE.itemsize == 48 and ROW_STATS_DTYPE.itemsize == 32
 
+# include/ks_sweep.h
+CHECK_DTYPE = np.dtype([("flags", "<u4"), ("disturbed", "<u4"), ("lo", "<i4"), ("hi", "<i4"), ("med_lo", "<u4"),
+                        ("med_hi", "<u4"), ("mad_lo", "<u4"), ("mad_hi", "<u4")])
+LINE_DTYPE = np.dtype([("line", "<u4"), ("jstar", "<u4"), ("flags", "<u4"), ("pad", "<u4"), ("jump", "<f8")])
+assert CHECK_DTYPE.itemsize == 32 and LINE_DTYPE.itemsize == 24
+KS_CHECK_EDGE_LOW = 1
+KS_CHECK_EDGE_HIGH = 2
+KS_CHECK_NO_CHANGE = 4
+KS_CHECK_DISTURBED = 8
+KS_CHECK_INVALID = 0x80000000
+KS_LINE_INCONCLUSIVE = 1
+KS_LINE_NO_INCREASE = 2
+KS_LINE_NO_MAX_LIKE = 4
+KS_LINE_INVALID = 0x80000000
+
 
 class ks_params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("c_alpha", ctypes.c_double), ("max_K", ctypes.c_uint32),
@@ -105,6 +120,9 @@ _SIGNATURES = {
     "ks_segment_batch": ([_vp, _vp, _u64, _vp, _u32, _vp, _u32, _u32, _vp, _vp, _vp], ctypes.c_int),
     "ks_probe_read": ([_vp, _u64, _u32, _u32, _vp, _vp], ctypes.c_int),
     "ks_stats_batch": ([_vp, _vp, _u64, _vp, _u32, _u32, _vp, _u64, _vp], ctypes.c_int),
+    "ks_check_batch": ([_vp, _vp, _u32, _u32, _vp, _vp, _u64, _u32, _u32, _vp, _vp], ctypes.c_int),
+    "ks_align_batch": ([_vp, _vp, _u32, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "ks_line_batch": ([_vp, _vp, _u32, _vp, _u64, _u32, _vp, _vp, _vp], ctypes.c_int),
     "ks_train_step": ([_vp, _vp, _vp, _u64, _vp, _vp, _u32, _u32, ctypes.c_float, _vp, _vp], ctypes.c_int),
 }
 
@@ -332,6 +350,34 @@ def ks_stats_batch(ctx, samples, desc, num_series: int, max_K: int, out, stream=
                               _addr(desc, 24 * num_series, "desc"), num_series, max_K, _addr(out, None, "out"),
                               _nelem(out, 32), _stream(stream))
     _check(rc, "ks_stats_batch")
+
+
+def ks_check_batch(ctx, desc, num_series: int, max_K: int, results, stats, out, edge: int = 4, k: int = 5,
+                   stream=None) -> None:
+    """Workflow step 3 on every sweep: outlier check and widening from the detection (ks_result)
+    and the per-step statistics (ROW_STATS_DTYPE rows); out: CHECK_DTYPE records (include/ks_sweep.h)."""
+    rc = lib().ks_check_batch(ctx, _addr(desc, 24 * num_series, "desc"), num_series, max_K,
+                              _addr(results, 48 * num_series, "results"), _addr(stats, None, "stats"),
+                              _nelem(stats, 32), edge, k, _addr(out, 32 * num_series, "out"), _stream(stream))
+    _check(rc, "ks_check_batch")
+
+
+def ks_align_batch(measured, total, n: int, segments, aligned, distance, stream=None) -> None:
+    """Benchmarked segment sizes aligned to the nearest integer fraction of the reported size
+    (uint64 bytes in; uint32 k, float64 aligned size and distance out)."""
+    rc = lib().ks_align_batch(_addr(measured, 8 * n, "measured"), _addr(total, 8 * n, "total"), n,
+                              _addr(segments, 4 * n, "segments"), _addr(aligned, 8 * n, "aligned"),
+                              _addr(distance, 8 * n, "distance"), _stream(stream))
+    _check(rc, "ks_align_batch")
+
+
+def ks_line_batch(ctx, desc, num_exp: int, stats, J: int, strides, out, stream=None) -> None:
+    """Cache-line-size scoring of every experiment (K = J A rows of ROW_STATS_DTYPE p50s); out:
+    LINE_DTYPE records (include/ks_sweep.h)."""
+    rc = lib().ks_line_batch(ctx, _addr(desc, 24 * num_exp, "desc"), num_exp, _addr(stats, None, "stats"),
+                             _nelem(stats, 32), J, _addr(strides, 4 * J, "strides"), _addr(out, 24 * num_exp, "out"),
+                             _stream(stream))
+    _check(rc, "ks_line_batch")
 
 
 def ks_probe_read(words, grid: int, unroll: int, sink, stream=None) -> None:

@@ -36,6 +36,7 @@ KS_SOURCES = [
     "csrc/ks_segment.hip",
     "csrc/ks_probe.hip",
     "csrc/ks_stats.hip",
+    "csrc/ks_sweep.hip",
 ]
 
 TARGETS = {

@@ -175,3 +175,36 @@ def philox4x32_10(ctr, key) -> tuple[int, int, int, int]:
 
 def math_fn(which: str, x: float) -> float:
     return _load().syn_math({"exp": 0, "log": 1, "cos2pi": 2}[which], float(x))
+
+
+def line_experiments(num_exp: int, J: int = 16, A: int = 32, N: int = 256, seed: int = SEED_BASE + 6,
+                     stride_step: int = 16) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Cache-line-size experiments (Section "Cache Line Size benchmarks"): for each of
+    num_exp caches, J strides stride_step * (j + 1) bytes (stride 0 the pivot, J - 1 the
+    MAX) x A array sizes around and above the cache size x N latencies. A stride up to the
+    line size L touches every line, so the miss share rises with the array size from 0.3
+    to 1; a stride s > L skips lines and reaches L / s of it. Latency = lo + (hi - lo) x
+    miss share, hi ~ U[500, 900], lo ~ U[200, 400] cycles, L a power of two drawn from
+    the strides below the largest power of two; per sample lognormal jitter sigma 0.05
+    and 1% outliers x U[1, 5] (numpy's Generator, seeded).
+
+    Returns (samples uint32 [num_exp * J * A * N], strides uint32 [J], planted L [num_exp])."""
+    rng = np.random.default_rng(seed)
+    strides = np.array([stride_step * (j + 1) for j in range(J)], np.uint32)
+    pow2 = [int(s) for s in strides if (int(s) & (int(s) - 1)) == 0][:-1]
+    if not pow2:
+        raise ValueError("the strides need two powers of two")
+    lines = np.array(pow2, np.uint32)[rng.integers(0, len(pow2), num_exp)]
+    hi = rng.uniform(500, 900, num_exp)
+    lo = rng.uniform(200, 400, num_exp)
+    frac = np.linspace(0.3, 1.0, A)
+    share = np.where(strides[None, :, None] <= lines[:, None, None], frac[None, None, :],
+                     frac[None, None, :] * (lines[:, None, None] / strides[None, :, None].astype(np.float64)))
+    lat = lo[:, None, None] + (hi - lo)[:, None, None] * share          # [E][J][A]
+    out = np.empty((num_exp, J, A, N), np.uint32)
+    for e in range(num_exp):  # one experiment at a time bounds the temporaries
+        x = lat[e][:, :, None] * np.exp(0.05 * rng.standard_normal((J, A, N)))
+        o = rng.random((J, A, N)) < 0.01
+        x = np.where(o, lat[e][:, :, None] * rng.uniform(1, 5, (J, A, N)), x)
+        out[e] = np.clip(np.rint(x), 1, 2**32 - 1).astype(np.uint32)
+    return out.reshape(-1), strides, lines
