@@ -224,7 +224,7 @@ int scan_with(ks_ctx* ctx, const ScanArgs& a, int kc, const LaunchCfg& cfg, hipS
   const bool split = cfg.mode == KS_LAUNCH_PERSISTENT;
   if (int rc = ensure_workspace(ctx, a.num_series, split ? (uint64_t)a.num_series * a.max_K : 0)) return rc;
   ScanArgs b = a;
-  b.chunk = split ? cfg.chunk_bytes : 0xffffffffu;  // the ordered grid never splits
+  b.chunk = split ? cfg.chunk_bytes : ks::kNoSplit;  // the ordered grid never splits
   b.ws = workspace_of(ctx);
   return launch_plan(ctx, kc, cfg.mode, b, cfg.graph != 0, st);
 }

@@ -40,10 +40,14 @@ struct Workspace {
 constexpr uint32_t kMaxChunks = 64;
 constexpr int kPlanNT = 1024;
 constexpr int kBuckets = 48;
+constexpr uint32_t kNoSplit = 0xffffffffu;  // chunk_bytes of the ordered grid: one item per series
 
 // Rows per work item: whole rows, about chunk_bytes of samples, at most
-// kMaxChunks items per series.
+// kMaxChunks items per series; the whole series when chunk_bytes is kNoSplit
+// (the ordered grid dispatches exactly one workgroup per series, so a series
+// of more than 4 GiB must not become several items there).
 __device__ __forceinline__ uint32_t rows_per_item(uint32_t K, uint32_t N, uint32_t chunk_bytes) {
+  if (chunk_bytes == kNoSplit) return K;
   uint64_t rpc = chunk_bytes / (4ull * N);
   if (rpc < 1) rpc = 1;
   const uint32_t minr = (K + kMaxChunks - 1) / kMaxChunks;

@@ -76,3 +76,45 @@ def test_recipe5_full_8192_series():
     g = run_full(5, 8, 5)
     assert len(g) == 8192
     assert math.isfinite(float(g["lambda"].max()))
+
+
+@pytest.mark.parametrize("launch", [(P.KS_LAUNCH_ORDERED, 1 << 20, 1), (P.KS_LAUNCH_ORDERED, 1 << 20, 0),
+                                    (P.KS_LAUNCH_PERSISTENT, 1 << 20, 1)],
+                         ids=["ordered-graph", "ordered-direct", "persistent"])
+def test_series_above_4gib_among_small_ones(launch):
+    """A series of 64 rows x 2^24 samples (4 GiB of samples, more than a 32-bit
+    byte count) among three small ones. The ordered plan must keep it one work
+    item, so that its one-workgroup-per-series grid still covers every series.
+    The big series is a noise-free step (rows < c0 at 120 cycles, the rest at
+    121): its keys are Q = 0 below c0 and N above, so the closed form holds,
+    c* = c0 and U* = c0 (K - c0); the small series are checked by the oracle."""
+    import torch
+
+    K, N, c0 = 64, 1 << 24, 40
+    big = K * N
+    b = S.make_batch(2, num_series=3, first_series=900)
+    xs = S.fill_host(b)
+    buf = torch.empty(big + len(xs), dtype=torch.int32, device="cuda")
+    buf[:c0 * N].fill_(120)
+    buf[c0 * N:big].fill_(121)
+    buf[big:] = torch.from_numpy(xs.view(np.int32)).cuda()
+    offs = np.concatenate([[0], big + b.specs["offset"].astype(np.int64)])
+    d = P.make_desc(offs, np.concatenate([[K], b.specs["K"]]), np.concatenate([[N], b.specs["N"]]))
+    prm = P.ks_params_init(0.05)
+    prm.max_K = 256
+    out = P.empty_results(4)
+    out.fill_(0xA5)
+    with P.Context(0) as ctx:
+        P.ks_launch_set(ctx.handle, 256, 4, *launch)
+        P.ks_scan_batch(ctx.handle, buf, P.to_device(d), 4, prm, out)
+        torch.cuda.synchronize()
+    g = P.results_to_numpy(out)
+    assert (g[0]["cp"], g[0]["n"], g[0]["m"], g[0]["U"]) == (c0, c0, K - c0, c0 * (K - c0))
+    assert g[0]["D"] == 1.0 and g[0]["flags"] & P.KS_SIGNIFICANT
+    for t in range(1, 4):
+        o0, k, n_ = int(d[t]["offset"]) - big, int(d[t]["K"]), int(d[t]["N"])
+        o = O.scan_series(xs[o0:o0 + k * n_].reshape(k, n_))
+        assert (g[t]["cp"], g[t]["U"], g[t]["n"], g[t]["m"]) == (o["cp"], o["U"], o["n"], o["m"]), t
+        assert g[t]["flags"] == (P.KS_SIGNIFICANT if o["significant"] else 0), t
+    del buf
+    torch.cuda.empty_cache()
