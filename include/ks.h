@@ -272,7 +272,10 @@ int ks_cnn_forward(ks_ctx *ctx, const ks_model *model, const float *features, ui
  * proposal[s] = argmax of the logits over rows 1..K-1 (smallest on ties) and
  * confidence[s] = softmax mass of the rows within +-params->w of it (device
  * int32 / float arrays of num_series). Skipped series get proposal 0,
- * confidence 0. features: as ks_features (nullable). */
+ * confidence 0. features: as ks_features (nullable).
+ * model == NULL proposes without a network (the baseline a trained network is
+ * measured against): the row t in 1..K-1 with the largest |f_t - f_(t-1)| of
+ * the per-row median (feature 5), ties to the smaller t, confidence 1. */
 int ks_propose(ks_ctx *ctx, const ks_model *model, const uint32_t *samples, uint64_t num_samples,
                const ks_desc *desc, uint32_t num_series, const ks_params *params, int32_t *proposal,
                float *confidence, float *features, uint64_t feature_rows, void *stream);
@@ -294,6 +297,53 @@ int ks_refine(ks_ctx *ctx, const ks_desc *desc, uint32_t num_series, uint64_t nu
  * (the batch's mean loss before the update). */
 int ks_train_step(ks_ctx *ctx, ks_model *model, const float *features, uint64_t feature_rows, const ks_desc *desc,
                   const int32_t *labels, uint32_t num_series, uint32_t max_K, float lr, float *loss, void *stream);
+
+/* Gradient, at the model's current weights, of L = sum over series s and rows
+ * t < K_s of dlogits[aux_offset + t] * logit[aux_offset + t]: the training
+ * step's forward and backward passes (same kernels, same bf16 rounding of the
+ * layer inputs, weights and output gradients, fp32 accumulation), with the
+ * logit gradient given by the caller instead of the softmax cross-entropy's.
+ * For other losses of the logits (pass dL/dlogit), and for checking the
+ * backward pass on its own.
+ *   features  device float[feature_rows][9], as ks_cnn_forward
+ *   dlogits   device float[dlogit_rows], row aux_offset + t of series s;
+ *             a series whose rows do not fit in dlogit_rows contributes 0
+ *   grads     device float[KS_CNN_PARAMS], written in the parameter layout
+ * The weights, the Adam state and the gradient kept for ks_model_grads are not
+ * changed. Skipped series (K > max_K or a bad shape) contribute nothing;
+ * num_series == 0 writes a zero gradient. KS_E_INVALID on a NULL pointer,
+ * KS_E_RANGE on max_K outside [2, KS_MAX_K], KS_E_NOMEM if the training
+ * buffers cannot grow. */
+int ks_cnn_backward(ks_ctx *ctx, const ks_model *model, const float *features, uint64_t feature_rows,
+                    const ks_desc *desc, uint32_t num_series, uint32_t max_K, const float *dlogits,
+                    uint64_t dlogit_rows, float *grads, void *stream);
+
+/* The network's intermediate values, for checking each layer on its own
+ * inputs: the training step's forward pass (one kernel per layer) on caller
+ * features and, when labels or dlogits is given, its backward pass.
+ *   labels     device int32[num_series], nullable: when given, the logit
+ *              gradient is the training step's (softmax cross-entropy, label
+ *              -1 skips a series); otherwise
+ *   dlogits    device float[dlogit_rows], nullable: the caller's logit
+ *              gradient as for ks_cnn_backward
+ *   acts       device, nullable, float[trace_rows][KS_CNN_TRACE_ACTS]: row
+ *              aux_offset + t of series s holds the bf16 network input x0[11],
+ *              the bf16 activations a1[64], a2[64], a3[64] (as floats) and the
+ *              fp32 logit
+ *   grads_in   device, nullable, float[trace_rows][KS_CNN_TRACE_GRADS]: the
+ *              fp32 logit gradient, then the fp32 gradients at the
+ *              pre-activations y2, y1, y0 [64 each] (masked by ReLU; the next
+ *              layer down takes their bf16 roundings)
+ *   grads      device, nullable, float[KS_CNN_PARAMS]: the parameter gradient
+ * A series is written only when aux_offset + K <= trace_rows. The model is not
+ * changed. KS_E_INVALID on a NULL pointer, or grads_in / grads without labels
+ * or dlogits; KS_E_RANGE on max_K outside [2, KS_MAX_K]. */
+#define KS_CNN_TRACE_ACTS 204u
+#define KS_CNN_TRACE_GRADS 193u
+int ks_cnn_trace(ks_ctx *ctx, const ks_model *model, const float *features, uint64_t feature_rows,
+                 const ks_desc *desc, uint32_t num_series, uint32_t max_K, const int32_t *labels,
+                 const float *dlogits, uint64_t dlogit_rows, float *acts, float *grads_in, uint64_t trace_rows,
+                 float *grads, void *stream);
 
 /* ------------------------------------------------------------ segmentation */
 

@@ -20,6 +20,8 @@ KS_MAX_K = 2048
 KS_MAX_N = 1 << 24
 KS_CNN_PARAMS = 44993
 KS_FEATURE_MAX_N = 4096
+KS_CNN_TRACE_ACTS = 204
+KS_CNN_TRACE_GRADS = 193
 
 KS_OK = 0
 KS_E_INVALID = -1
@@ -124,6 +126,8 @@ _SIGNATURES = {
     "ks_align_batch": ([_vp, _vp, _u32, _vp, _vp, _vp, _vp], ctypes.c_int),
     "ks_line_batch": ([_vp, _vp, _u32, _vp, _u64, _u32, _vp, _vp, _vp], ctypes.c_int),
     "ks_train_step": ([_vp, _vp, _vp, _u64, _vp, _vp, _u32, _u32, ctypes.c_float, _vp, _vp], ctypes.c_int),
+    "ks_cnn_backward": ([_vp, _vp, _vp, _u64, _vp, _u32, _u32, _vp, _u64, _vp, _vp], ctypes.c_int),
+    "ks_cnn_trace": ([_vp, _vp, _vp, _u64, _vp, _u32, _u32, _vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp], ctypes.c_int),
 }
 
 
@@ -393,6 +397,31 @@ def ks_train_step(ctx, model, features, desc, labels, num_series: int, max_K: in
                              _addr(desc, 24 * num_series, "desc"), _addr(labels, 4 * num_series, "labels"), num_series,
                              max_K, lr, _addr(loss, 4, "loss"), _stream(stream))
     _check(rc, "ks_train_step")
+
+
+def ks_cnn_backward(ctx, model, features, desc, num_series: int, max_K: int, dlogits, grads, stream=None) -> None:
+    """Gradient of sum(dlogits * logits) at the model's weights; grads: float32 device buffer of
+    KS_CNN_PARAMS values (parameter layout)."""
+    rc = lib().ks_cnn_backward(ctx, model, _addr(features, None, "features"), _nelem(features, 36),
+                               _addr(desc, 24 * num_series, "desc"), num_series, max_K,
+                               _addr(dlogits, None, "dlogits"), _nelem(dlogits, 4),
+                               _addr(grads, 4 * KS_CNN_PARAMS, "grads"), _stream(stream))
+    _check(rc, "ks_cnn_backward")
+
+
+def ks_cnn_trace(ctx, model, features, desc, num_series: int, max_K: int, labels=None, dlogits=None, acts=None,
+                 grads_in=None, grads=None, stream=None) -> None:
+    """Per-layer values of the network: acts (KS_CNN_TRACE_ACTS floats per row), grads_in
+    (KS_CNN_TRACE_GRADS floats per row) and the parameter gradient (device float32 buffers)."""
+    rows = max(_nelem(acts, 4 * KS_CNN_TRACE_ACTS), _nelem(grads_in, 4 * KS_CNN_TRACE_GRADS))
+    if acts is not None and grads_in is not None:
+        rows = min(_nelem(acts, 4 * KS_CNN_TRACE_ACTS), _nelem(grads_in, 4 * KS_CNN_TRACE_GRADS))
+    rc = lib().ks_cnn_trace(ctx, model, _addr(features, None, "features"), _nelem(features, 36),
+                            _addr(desc, 24 * num_series, "desc"), num_series, max_K,
+                            _addr(labels, 4 * num_series, "labels"), _addr(dlogits, None, "dlogits"),
+                            _nelem(dlogits, 4), _addr(acts, None, "acts"), _addr(grads_in, None, "grads_in"), rows,
+                            _addr(grads, 4 * KS_CNN_PARAMS, "grads"), _stream(stream))
+    _check(rc, "ks_cnn_trace")
 
 
 class Model:

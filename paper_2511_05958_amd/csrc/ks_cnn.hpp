@@ -491,6 +491,13 @@ __global__ __launch_bounds__(NTC) void adam_kernel(float* __restrict__ theta, fl
   theta[p] -= lr * (m / bc1) / (sqrtf(v / bc2) + 1e-8f);
 }
 
+// p[i] = 0 for i < n (a plain fill kernel rather than a memset node, so that a
+// captured graph replays it like any other kernel).
+__global__ __launch_bounds__(NTC) void zero_kernel(float* __restrict__ p, uint32_t n) {
+  const uint32_t i = blockIdx.x * NTC + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
 // ---------------------------------------------------------------- series heads
 
 // Number of labels >= 1 in the batch (the series that enter the loss).
@@ -589,6 +596,42 @@ __global__ __launch_bounds__(NTC) void softmax_kernel(const float* __restrict__ 
   }
 }
 
+// Proposal without the network: the row after the largest jump of the per-row
+// median (feature 5, the fifth decile), |f_t - f_(t-1)| in FP64 (exact for
+// floats), ties to the smaller row; confidence 1 (always refined). One wave per
+// series, features from the feature pass's slot rows.
+__global__ __launch_bounds__(NTC) void median_jump_kernel(const float* __restrict__ feat, uint32_t num_series,
+                                                          uint32_t SR, const uint32_t* __restrict__ Ks,
+                                                          int32_t* __restrict__ proposal,
+                                                          float* __restrict__ conf) {
+  const uint32_t lane = lane_id();
+  const uint32_t s = blockIdx.x * (NTC / kWave) + wave_id();
+  if (s >= num_series) return;
+  const uint32_t K = Ks[s];
+  const uint64_t base = (uint64_t)s * SR + 2;
+  double best = -1.0;
+  uint32_t arg = 0;
+  for (uint32_t t = 1 + lane; t < K; t += kWave) {
+    const double j = fabs((double)feat[(base + t) * 9 + 4] - (double)feat[(base + t - 1) * 9 + 4]);
+    if (j > best) {  // t grows within a lane: the first maximum is kept
+      best = j;
+      arg = t;
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double bo = __shfl_xor(best, o);
+    const uint32_t ao = (uint32_t)__shfl_xor((int)arg, o);
+    if (bo > best || (bo == best && ao < arg && ao != 0)) {
+      best = bo;
+      arg = ao;
+    }
+  }
+  if (lane == 0) {
+    proposal[s] = K >= 2 ? (int32_t)arg : 0;
+    conf[s] = K >= 2 ? 1.0f : 0.0f;
+  }
+}
+
 // Caller features (fp32 [rows at aux_offset][9]) -> network input rows
 // (bf16, 16 channels) in the slot layout, plus each series' K (0 if invalid).
 __global__ __launch_bounds__(NTC) void pack_features_kernel(const float* __restrict__ feat, uint64_t feat_rows,
@@ -615,6 +658,72 @@ __global__ __launch_bounds__(NTC) void pack_features_kernel(const float* __restr
     x0[((uint64_t)s * SR + r) * 16 + k] = b;
   }
   if (threadIdx.x == 0) Ks[s] = K;
+}
+
+// Caller logit gradients (fp32 rows aux_offset + t) -> the backward pass's
+// input in the slot layout: bf16 and fp32 copies of channel 0 (16 channels, the
+// others zero), zero on rows outside every series.
+__global__ __launch_bounds__(NTC) void pack_dlogits_kernel(const float* __restrict__ dz, uint64_t dz_rows,
+                                                           const ks_desc* __restrict__ desc, uint32_t num_series,
+                                                           uint32_t SR, const uint32_t* __restrict__ Ks,
+                                                           uint16_t* __restrict__ dY, float* __restrict__ dYf) {
+  const uint32_t s = blockIdx.x;
+  if (s >= num_series) return;
+  const ks_desc d = desc[s];
+  uint32_t K = Ks[s];
+  if (!(d.aux_offset <= dz_rows && K <= dz_rows - d.aux_offset)) K = 0;
+  for (uint32_t q = threadIdx.x; q < SR * 16; q += NTC) {
+    const uint32_t r = q / 16, c = q - r * 16;
+    const float v = (c == 0 && r >= 2 && r - 2 < K) ? dz[d.aux_offset + r - 2] : 0.0f;
+    dY[((uint64_t)s * SR + r) * 16 + c] = f2bf(v);
+    dYf[((uint64_t)s * SR + r) * 16 + c] = v;
+  }
+}
+
+// Per-layer values of one forward (and backward) pass -> caller rows
+// aux_offset + t, as floats: acts row = x0[11] a1[64] a2[64] a3[64] logit
+// (KS_CNN_TRACE_ACTS), gin row = dlogit, then the gradients at y2, y1, y0
+// [64 each] (KS_CNN_TRACE_GRADS). dyf0 == nullptr: no backward values.
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__global__ __launch_bounds__(NTC) void trace_copy_kernel(const ks_desc* __restrict__ desc, uint32_t num_series,
+                                                         uint32_t SR, const uint32_t* __restrict__ Ks,
+                                                         const uint16_t* __restrict__ x0,
+                                                         const uint16_t* __restrict__ a1,
+                                                         const uint16_t* __restrict__ a2,
+                                                         const uint16_t* __restrict__ a3,
+                                                         const float* __restrict__ logits,
+                                                         const float* __restrict__ dz, const float* __restrict__ dyf0,
+                                                         const float* __restrict__ dyf1, const float* __restrict__ dyf2,
+                                                         float* __restrict__ acts, float* __restrict__ gin,
+                                                         uint64_t out_rows) {
+  constexpr uint32_t NA = 11 + 3 * 64 + 1, NG = 1 + 3 * 64;
+  const uint32_t s = blockIdx.x;
+  if (s >= num_series) return;
+  const ks_desc d = desc[s];
+  const uint32_t K = Ks[s];
+  if (!(d.aux_offset <= out_rows && K <= out_rows - d.aux_offset)) return;
+  for (uint32_t q = threadIdx.x; q < K * NA && acts; q += NTC) {
+    const uint32_t t = q / NA, c = q - t * NA;
+    const uint64_t row = (uint64_t)s * SR + 2 + t;
+    float v;
+    if (c < 11) v = bf2f(x0[row * 16 + c]);
+    else if (c < 75) v = bf2f(a1[row * 64 + (c - 11)]);
+    else if (c < 139) v = bf2f(a2[row * 64 + (c - 75)]);
+    else if (c < 203) v = bf2f(a3[row * 64 + (c - 139)]);
+    else v = logits[row];
+    acts[(d.aux_offset + t) * NA + c] = v;
+  }
+  for (uint32_t q = threadIdx.x; q < K * NG && gin && dyf0; q += NTC) {
+    const uint32_t t = q / NG, c = q - t * NG;
+    const uint64_t row = (uint64_t)s * SR + 2 + t;
+    float v;
+    if (c == 0) v = dz[row * 16];
+    else if (c < 65) v = dyf0[row * 64 + (c - 1)];
+    else if (c < 129) v = dyf1[row * 64 + (c - 65)];
+    else v = dyf2[row * 64 + (c - 129)];
+    gin[(d.aux_offset + t) * NG + c] = v;
+  }
 }
 
 // Logits in the slot layout -> caller rows (aux_offset + t), nullable output.

@@ -59,8 +59,8 @@ struct LearnBuffers {
   // training
   uint16_t* dy16 = nullptr;   // [rows][16] bf16: logit gradient
   float* dy16f = nullptr;
-  uint16_t* dy[2] = {nullptr, nullptr};  // [rows][64] bf16
-  float* dyf[2] = {nullptr, nullptr};
+  uint16_t* dy[3] = {nullptr, nullptr, nullptr};  // [rows][64] bf16: gradients at y2, y1, y0
+  float* dyf[3] = {nullptr, nullptr, nullptr};     // the same in fp32 (before the bf16 rounding)
   float* part = nullptr;      // weight-gradient partials
   float* grad[4] = {nullptr, nullptr, nullptr, nullptr};  // reduced, per layer
   uint32_t* nsig = nullptr;

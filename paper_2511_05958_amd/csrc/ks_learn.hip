@@ -21,7 +21,7 @@ namespace ks_host {
 
 void free_learn(LearnBuffers& b) {
   void* ptrs[] = {b.s1, b.s2lo, b.s2hi, b.smin, b.K, b.feat, b.x0, b.act[0], b.act[1], b.act[2], b.logits,
-                  b.dy16, b.dy16f, b.dy[0], b.dy[1], b.dyf[0], b.dyf[1], b.part, b.grad[0], b.grad[1],
+                  b.dy16, b.dy16f, b.dy[0], b.dy[1], b.dy[2], b.dyf[0], b.dyf[1], b.dyf[2], b.part, b.grad[0], b.grad[1],
                   b.grad[2], b.grad[3], b.nsig};
   for (void* p : ptrs) (void)hipFree(p);
   b = LearnBuffers{};
@@ -58,7 +58,8 @@ int ensure_learn(ks_ctx* c, uint64_t rows, uint64_t series, bool train) {
   if (ok && T) {
     const uint64_t part = (uint64_t)kDwGrid * (64 * 320 + 64);
     ok = alloc(b.dy16, R * 16) && alloc(b.dy16f, R * 16) && alloc(b.dy[0], R * 64) && alloc(b.dy[1], R * 64) &&
-         alloc(b.dyf[0], R * 64) && alloc(b.dyf[1], R * 64) && alloc(b.part, part) && alloc(b.grad[0], 64 * 80 + 64) &&
+         alloc(b.dy[2], R * 64) && alloc(b.dyf[0], R * 64) && alloc(b.dyf[1], R * 64) && alloc(b.dyf[2], R * 64) &&
+         alloc(b.part, part) && alloc(b.grad[0], 64 * 80 + 64) &&
          alloc(b.grad[1], 64 * 320 + 64) && alloc(b.grad[2], 64 * 320 + 64) && alloc(b.grad[3], 16 * 320 + 16) &&
          alloc(b.nsig, 4);
     b.cap_part = part;
@@ -107,6 +108,37 @@ hipError_t forward_infer(ks_ctx* c, const ks_model* m, uint64_t rows, uint32_t S
   const uint32_t g = (uint32_t)(tiles < cap ? (tiles ? tiles : 1) : cap);
   hipLaunchKernelGGL(C::fused_forward_kernel, dim3(g), dim3(C::NTC), 0, st, b.x0, rows, SR, b.K, m->wf[0], m->wf[1],
                      m->wf[2], m->wf[3], m->b[0], m->b[1], m->b[2], m->b[3], b.logits);
+  return hipGetLastError();
+}
+
+// Backward pass over the slot rows from the logit gradient in dy16 / dy16f
+// (bf16 / fp32, channel 0), with the activations of the last forward():
+// the gradients at the pre-activations y2, y1, y0 in dy / dyf[0..2] and the
+// per-layer weight and bias gradients reduced into grad[0..3].
+hipError_t backward(ks_ctx* c, const ks_model* model, uint64_t rows, uint32_t SR, hipStream_t st) {
+  LearnBuffers& b = c->learn;
+  const uint64_t tiles = (rows + C::TM - 1) / C::TM;
+  const uint32_t G = (uint32_t)(tiles < kDwGrid ? tiles : kDwGrid);
+  const uint32_t gc = conv_grid(c, rows);
+  auto reduce = [&](float* dst, uint32_t n) {
+    hipLaunchKernelGGL(C::reduce_parts_kernel, dim3((n + C::NTC - 1) / C::NTC), dim3(C::NTC), 0, st, b.part, G, n,
+                       dst);
+  };
+  // layer 3 (64 -> 1), then 2, 1 (64 -> 64), then 0 (11 -> 64)
+  hipLaunchKernelGGL((C::dw_kernel<64, 16>), dim3(G), dim3(C::NTC), 0, st, b.dy16, b.dy16f, b.act[2], rows, b.part);
+  reduce(b.grad[3], C::DwShape<64, 16>::PART);
+  hipLaunchKernelGGL((C::conv_kernel<16, 64, C::EPI_BWD>), dim3(gc), dim3(C::NTC), 0, st, b.dy16, model->wb[3],
+                     (const float*)nullptr, rows, SR, b.K, b.dy[0], b.dyf[0], b.act[2]);
+  hipLaunchKernelGGL((C::dw_kernel<64, 64>), dim3(G), dim3(C::NTC), 0, st, b.dy[0], b.dyf[0], b.act[1], rows, b.part);
+  reduce(b.grad[2], C::DwShape<64, 64>::PART);
+  hipLaunchKernelGGL((C::conv_kernel<64, 64, C::EPI_BWD>), dim3(gc), dim3(C::NTC), 0, st, b.dy[0], model->wb[2],
+                     (const float*)nullptr, rows, SR, b.K, b.dy[1], b.dyf[1], b.act[1]);
+  hipLaunchKernelGGL((C::dw_kernel<64, 64>), dim3(G), dim3(C::NTC), 0, st, b.dy[1], b.dyf[1], b.act[0], rows, b.part);
+  reduce(b.grad[1], C::DwShape<64, 64>::PART);
+  hipLaunchKernelGGL((C::conv_kernel<64, 64, C::EPI_BWD>), dim3(gc), dim3(C::NTC), 0, st, b.dy[1], model->wb[1],
+                     (const float*)nullptr, rows, SR, b.K, b.dy[2], b.dyf[2], b.act[0]);
+  hipLaunchKernelGGL((C::dw_kernel<16, 64>), dim3(G), dim3(C::NTC), 0, st, b.dy[2], b.dyf[2], b.x0, rows, b.part);
+  reduce(b.grad[0], C::DwShape<16, 64>::PART);
   return hipGetLastError();
 }
 
@@ -362,7 +394,7 @@ int ks_cnn_forward(ks_ctx* ctx, const ks_model* model, const float* features, ui
 int ks_propose(ks_ctx* ctx, const ks_model* model, const uint32_t* samples, uint64_t num_samples,
                const ks_desc* desc, uint32_t num_series, const ks_params* params, int32_t* proposal,
                float* confidence, float* features, uint64_t feature_rows, void* stream) {
-  if (!ctx || !model || !params) return KS_E_INVALID;
+  if (!ctx || !params) return KS_E_INVALID;
   if (int rc = check_params(params)) return rc;
   if (num_series == 0) return KS_OK;
   if (!proposal || !confidence) return KS_E_INVALID;
@@ -373,9 +405,15 @@ int ks_propose(ks_ctx* ctx, const ks_model* model, const uint32_t* samples, uint
   hipStream_t st = (hipStream_t)stream;
   LearnBuffers& b = ctx->learn;
   const uint32_t SR = b.stamp_SR;
+  const uint32_t per = C::NTC / 64;
+  if (!model) {  // the method without the network: the largest jump of the per-row median
+    hipLaunchKernelGGL(C::median_jump_kernel, dim3((num_series + per - 1) / per), dim3(C::NTC), 0, st, b.feat,
+                       num_series, SR, b.K, proposal, confidence);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KS_OK : hip_fail(e, "propose");
+  }
   hipError_t e = forward_infer(ctx, model, (uint64_t)num_series * SR, SR, st);
   if (e == hipSuccess) {
-    const uint32_t per = C::NTC / 64;
     hipLaunchKernelGGL(C::softmax_kernel, dim3((num_series + per - 1) / per), dim3(C::NTC), 0, st, b.logits,
                        num_series, SR, b.K, (const int32_t*)nullptr, (const uint32_t*)nullptr, (float*)nullptr,
                        (uint16_t*)nullptr, (float*)nullptr, params->w, proposal, confidence);
@@ -433,35 +471,13 @@ int ks_train_step(ks_ctx* ctx, ks_model* model, const float* features, uint64_t 
   hipLaunchKernelGGL(C::count_labels_kernel, dim3(1), dim3(C::NTC), 0, st, labels, num_series, b.nsig);
   float* loss_acc = reinterpret_cast<float*>(b.nsig + 1);  // discarded when the caller wants no loss
   if (loss) {
-    e = hipMemsetAsync(loss, 0, sizeof(float), st);
-    if (e != hipSuccess) return hip_fail(e, "loss reset");
+    hipLaunchKernelGGL(C::zero_kernel, dim3(1), dim3(C::NTC), 0, st, loss, 1u);
     loss_acc = loss;
   }
   const uint32_t per = C::NTC / 64;
   hipLaunchKernelGGL(C::softmax_kernel, dim3((num_series + per - 1) / per), dim3(C::NTC), 0, st, b.logits, num_series,
                      SR, b.K, labels, b.nsig, loss_acc, b.dy16, b.dy16f, 0u, (int32_t*)nullptr, (float*)nullptr);
-  // backward: layer 3 (64 -> 1), then 2, 1 (64 -> 64), then 0 (9 -> 64)
-  const uint64_t tiles = (rows + C::TM - 1) / C::TM;
-  const uint32_t G = (uint32_t)(tiles < kDwGrid ? tiles : kDwGrid);
-  const uint32_t gc = conv_grid(ctx, rows);
-  auto reduce = [&](float* dst, uint32_t n) {
-    hipLaunchKernelGGL(C::reduce_parts_kernel, dim3((n + C::NTC - 1) / C::NTC), dim3(C::NTC), 0, st, b.part, G, n,
-                       dst);
-  };
-  hipLaunchKernelGGL((C::dw_kernel<64, 16>), dim3(G), dim3(C::NTC), 0, st, b.dy16, b.dy16f, b.act[2], rows, b.part);
-  reduce(b.grad[3], C::DwShape<64, 16>::PART);
-  hipLaunchKernelGGL((C::conv_kernel<16, 64, C::EPI_BWD>), dim3(gc), dim3(C::NTC), 0, st, b.dy16, model->wb[3],
-                     (const float*)nullptr, rows, SR, b.K, b.dy[0], b.dyf[0], b.act[2]);
-  hipLaunchKernelGGL((C::dw_kernel<64, 64>), dim3(G), dim3(C::NTC), 0, st, b.dy[0], b.dyf[0], b.act[1], rows, b.part);
-  reduce(b.grad[2], C::DwShape<64, 64>::PART);
-  hipLaunchKernelGGL((C::conv_kernel<64, 64, C::EPI_BWD>), dim3(gc), dim3(C::NTC), 0, st, b.dy[0], model->wb[2],
-                     (const float*)nullptr, rows, SR, b.K, b.dy[1], b.dyf[1], b.act[1]);
-  hipLaunchKernelGGL((C::dw_kernel<64, 64>), dim3(G), dim3(C::NTC), 0, st, b.dy[1], b.dyf[1], b.act[0], rows, b.part);
-  reduce(b.grad[1], C::DwShape<64, 64>::PART);
-  hipLaunchKernelGGL((C::conv_kernel<64, 64, C::EPI_BWD>), dim3(gc), dim3(C::NTC), 0, st, b.dy[1], model->wb[1],
-                     (const float*)nullptr, rows, SR, b.K, b.dy[0], b.dyf[0], b.act[0]);
-  hipLaunchKernelGGL((C::dw_kernel<16, 64>), dim3(G), dim3(C::NTC), 0, st, b.dy[0], b.dyf[0], b.x0, rows, b.part);
-  reduce(b.grad[0], C::DwShape<16, 64>::PART);
+  if ((e = backward(ctx, model, rows, SR, st)) != hipSuccess) return hip_fail(e, "train backward");
   // Adam
   model->step += 1;
   const float bc1 = (float)(1.0 - std::pow(0.9, (double)model->step));
@@ -471,6 +487,91 @@ int ks_train_step(ks_ctx* ctx, ks_model* model, const float* features, uint64_t 
                      1);
   e = shadow(model, st);
   return e == hipSuccess ? KS_OK : hip_fail(e, "train step");
+}
+
+int ks_cnn_backward(ks_ctx* ctx, const ks_model* model, const float* features, uint64_t feature_rows,
+                    const ks_desc* desc, uint32_t num_series, uint32_t max_K, const float* dlogits,
+                    uint64_t dlogit_rows, float* grads, void* stream) {
+  if (!ctx || !model) return KS_E_INVALID;
+  if (max_K == 0) max_K = KS_MAX_K;
+  if (int rc = check_learn_args(desc, num_series, max_K)) return rc;
+  if (!grads) return KS_E_INVALID;
+  if (num_series && (!features || !dlogits)) return KS_E_INVALID;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t SR = slot_rows(max_K);
+  const uint64_t rows = (uint64_t)(num_series ? num_series : 1) * SR;
+  if (int rc = ensure_learn(ctx, rows, num_series ? num_series : 1, true)) return rc;
+  LearnBuffers& b = ctx->learn;
+  b.stamp_valid = false;
+  hipError_t e;
+  if (num_series == 0) {  // an empty batch has a zero gradient
+    hipLaunchKernelGGL(C::zero_kernel, dim3((C::kNumParams + C::NTC - 1) / C::NTC), dim3(C::NTC), 0, st, grads,
+                       C::kNumParams);
+    e = hipGetLastError();
+    return e == hipSuccess ? KS_OK : hip_fail(e, "gradient reset");
+  }
+  hipLaunchKernelGGL(C::pack_features_kernel, dim3(num_series), dim3(C::NTC), 0, st, features, feature_rows, desc,
+                     num_series, max_K, SR, b.x0, b.K);
+  if ((e = forward(ctx, model, rows, SR, st)) != hipSuccess) return hip_fail(e, "backward: forward");
+  hipLaunchKernelGGL(C::pack_dlogits_kernel, dim3(num_series), dim3(C::NTC), 0, st, dlogits, dlogit_rows, desc,
+                     num_series, SR, b.K, b.dy16, b.dy16f);
+  if ((e = backward(ctx, model, rows, SR, st)) != hipSuccess) return hip_fail(e, "backward");
+  // gather into the parameter layout (the optimizer kernel with its update off)
+  hipLaunchKernelGGL(C::adam_kernel, dim3((C::kNumParams + C::NTC - 1) / C::NTC), dim3(C::NTC), 0, st,
+                     (float*)nullptr, (float*)nullptr, (float*)nullptr, grads, b.grad[0], b.grad[1], b.grad[2],
+                     b.grad[3], 0.0f, 1.0f, 1.0f, 0);
+  e = hipGetLastError();
+  return e == hipSuccess ? KS_OK : hip_fail(e, "backward gather");
+}
+
+int ks_cnn_trace(ks_ctx* ctx, const ks_model* model, const float* features, uint64_t feature_rows,
+                 const ks_desc* desc, uint32_t num_series, uint32_t max_K, const int32_t* labels,
+                 const float* dlogits, uint64_t dlogit_rows, float* acts, float* grads_in, uint64_t trace_rows,
+                 float* grads, void* stream) {
+  if (!ctx || !model) return KS_E_INVALID;
+  if (max_K == 0) max_K = KS_MAX_K;
+  if (int rc = check_learn_args(desc, num_series, max_K)) return rc;
+  if (num_series == 0) return KS_OK;
+  if (!features) return KS_E_INVALID;
+  const bool bwd = labels || dlogits;
+  if ((grads_in || grads) && !bwd) return KS_E_INVALID;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t SR = slot_rows(max_K);
+  const uint64_t rows = (uint64_t)num_series * SR;
+  if (int rc = ensure_learn(ctx, rows, num_series, true)) return rc;
+  LearnBuffers& b = ctx->learn;
+  b.stamp_valid = false;
+  hipLaunchKernelGGL(C::pack_features_kernel, dim3(num_series), dim3(C::NTC), 0, st, features, feature_rows, desc,
+                     num_series, max_K, SR, b.x0, b.K);
+  hipError_t e = forward(ctx, model, rows, SR, st);
+  if (e != hipSuccess) return hip_fail(e, "trace forward");
+  if (labels) {  // the training step's logit gradient (its loss goes to a scratch word)
+    hipLaunchKernelGGL(C::count_labels_kernel, dim3(1), dim3(C::NTC), 0, st, labels, num_series, b.nsig);
+    const uint32_t per = C::NTC / 64;
+    hipLaunchKernelGGL(C::softmax_kernel, dim3((num_series + per - 1) / per), dim3(C::NTC), 0, st, b.logits,
+                       num_series, SR, b.K, labels, b.nsig, reinterpret_cast<float*>(b.nsig + 1), b.dy16, b.dy16f, 0u,
+                       (int32_t*)nullptr, (float*)nullptr);
+  } else if (dlogits) {
+    hipLaunchKernelGGL(C::pack_dlogits_kernel, dim3(num_series), dim3(C::NTC), 0, st, dlogits, dlogit_rows, desc,
+                       num_series, SR, b.K, b.dy16, b.dy16f);
+  }
+  if (bwd) {
+    if ((e = backward(ctx, model, rows, SR, st)) != hipSuccess) return hip_fail(e, "trace backward");
+    if (grads)
+      hipLaunchKernelGGL(C::adam_kernel, dim3((C::kNumParams + C::NTC - 1) / C::NTC), dim3(C::NTC), 0, st,
+                         (float*)nullptr, (float*)nullptr, (float*)nullptr, grads, b.grad[0], b.grad[1], b.grad[2],
+                         b.grad[3], 0.0f, 1.0f, 1.0f, 0);
+  }
+  if (acts || grads_in)
+    hipLaunchKernelGGL(C::trace_copy_kernel, dim3(num_series), dim3(C::NTC), 0, st, desc, num_series, SR, b.K, b.x0,
+                       b.act[0], b.act[1], b.act[2], b.logits, b.dy16f, bwd ? b.dyf[0] : nullptr, b.dyf[1], b.dyf[2],
+                       acts, grads_in, trace_rows);
+  e = hipGetLastError();
+  return e == hipSuccess ? KS_OK : hip_fail(e, "trace");
 }
 
 }  // extern "C"

@@ -3,6 +3,8 @@
     python -m paper_2511_05958_amd.train --series 200000 --epochs 10 --out model.ckpt
     python -m paper_2511_05958_amd.train --recipe 5 --first-series 1048576 --series 40000 \
         --val 4000 --chunk 1024 --out proposal_r5.ckpt
+    python -m paper_2511_05958_amd.train --calibrate --model proposal_r4.ckpt --recipe 4 \
+        --first-series 2097152 --series 40000 --target 0.9975
 
 Data: seeded synthetic sweeps of a training recipe, generated on the device in
 chunks (only the per-row features stay resident). Recipe 4 is the shape of
@@ -97,7 +99,8 @@ def train(ctx, model, feats, desc, labels, epochs: int, batch: int, lr: float, s
 
 
 def trivial_proposal(feats_host: np.ndarray, desc: np.ndarray) -> np.ndarray:
-    """Baseline without the network: the row after the largest jump of the per-row median (decile 5)."""
+    """Baseline without the network: the row after the largest jump of the per-row median (decile 5),
+    on the host (ks_propose with no model computes the same on the device)."""
     out = np.zeros(len(desc), np.int32)
     for s, dd in enumerate(desc):
         a, K = int(dd["aux_offset"]), int(dd["K"])
@@ -133,10 +136,12 @@ def evaluate(ctx, model, recipe: int, num_series: int, first_series: int, w: int
         ref = P.empty_results(n)
         prm.tau = 0.0
         P.ks_refine(ctx, d_dev, n, b.total_elems, prop, conf, prm, ref)
-        tp = torch.from_numpy(trivial_proposal(f.cpu().numpy().reshape(-1, 9), d)).to("cuda")
-        ones = torch.ones(n, dtype=torch.float32, device="cuda")
+        # the method without the network (ks_propose with no model), refined the same way
+        tp = torch.empty(n, dtype=torch.int32, device="cuda")
+        tc = torch.empty(n, dtype=torch.float32, device="cuda")
+        P.ks_propose(ctx, None, buf, d_dev, n, prm, tp, tc)
         ref_t = P.empty_results(n)
-        P.ks_refine(ctx, d_dev, n, b.total_elems, tp, ones, prm, ref_t)
+        P.ks_refine(ctx, d_dev, n, b.total_elems, tp, tc, prm, ref_t)
         g, r, rt = P.results_to_numpy(full), P.results_to_numpy(ref), P.results_to_numpy(ref_t)
         agree.append((g["cp"] == r["cp"]) & (g["U"] == r["U"]))
         agree_triv.append((g["cp"] == rt["cp"]) & (g["U"] == rt["U"]))
@@ -168,6 +173,42 @@ def calibrate_tau(agree: np.ndarray, conf: np.ndarray, target: float = 0.995) ->
     return 1.0, 1.0, 1.0
 
 
+def recalibrate(args) -> int:
+    """Calibrate tau of a trained model again, on held-out series of its recipe
+    (ids from --first-series on, disjoint from its training and validation
+    series and from the benchmark batches), at --target; the model's report gets
+    the new tau and a "calibration" record."""
+    import os
+
+    ctx = P.Context(0)
+    model = P.Model(ctx, seed=0)
+    P.ks_model_load(model.handle, args.model)
+    t0 = time.perf_counter()
+    ev = evaluate(ctx.handle, model.handle, args.recipe, args.series, args.first_series, chunk=args.chunk)
+    tau, agr, fb = calibrate_tau(ev["agree"], ev["confidence"], args.target)
+    rep_path = os.path.splitext(args.model)[0] + ".json"
+    with open(rep_path) as f:
+        rep = json.load(f)
+    rep_path = args.report or rep_path  # where the updated report goes
+    rep["tau"] = tau
+    rep["calibration"] = {"recipe": args.recipe, "first_series": args.first_series, "series": args.series,
+                          "target": args.target, "agreement_at_tau": agr, "fallback_at_tau": fb,
+                          "agreement_no_fallback": float(ev["agree"].mean()),
+                          "agreement_trivial_no_fallback": float(ev["agree_trivial"].mean()),
+                          "seconds": time.perf_counter() - t0,
+                          "command": "python -m paper_2511_05958_amd.train --calibrate " + " ".join(
+                              f"--{k.replace('_', '-')} {v}" for k, v in
+                              [("model", os.path.basename(args.model)), ("recipe", args.recipe),
+                               ("first_series", args.first_series), ("series", args.series),
+                               ("target", args.target), ("chunk", args.chunk)])}
+    with open(rep_path, "w") as f:
+        json.dump(rep, f, indent=1)
+    print(json.dumps(rep["calibration"] | {"tau": tau}), flush=True)
+    model.close()
+    ctx.close()
+    return 0
+
+
 def main() -> int:
     import torch
 
@@ -184,7 +225,12 @@ def main() -> int:
     ap.add_argument("--recipe", type=int, default=4, help="training recipe (4: recipe-2 shapes, own seed; 5: hard regime)")
     ap.add_argument("--first-series", type=int, default=0, help="first series id of the training data")
     ap.add_argument("--chunk", type=int, default=2048, help="series generated per device chunk")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only calibrate tau of --model on --series held-out series from --first-series on")
+    ap.add_argument("--model", default=None, help="trained model (with --calibrate)")
     args = ap.parse_args()
+    if args.calibrate:
+        return recalibrate(args)
     ctx = P.Context(0)
     model = P.Model(ctx, seed=args.seed)
     t0 = time.perf_counter()
