@@ -210,6 +210,27 @@ int ks_autotune(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, cons
                 uint32_t num_series, const ks_params *params, ks_result *out, void *stream, ks_launch *best,
                 float *best_ms);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): ks_scan_batch
+ * with the ordered launch plan (largest series first, one workgroup per
+ * series), run on a fixed scratch array in the library's device image
+ * instead of the context's workspace. It allocates nothing and launches the
+ * plan's two kernels directly (no hipGraph).
+ *   Arguments, results and per-series flags as ks_scan_batch; params->opts
+ *   is checked but the launch plan is always the ordered grid.
+ *   num_series <= KS_NOALLOC_MAX_SERIES, else KS_E_RANGE (nothing launched).
+ *   Scratch: 256 + 24 * KS_NOALLOC_MAX_SERIES bytes (12 MiB + 256 B) per
+ *   device, held until the process ends; ks_ctx_create resolves its address
+ *   on the context's device. Every call on one device shares it and each
+ *   call's planning kernel rewrites what the call reads, so calls in
+ *   sequence on any streams of one device are fine, but calls whose work
+ *   overlaps in time on one device race on the scratch and give undefined
+ *   results: order them on one stream, or wait between streams. */
+#define KS_NOALLOC_MAX_SERIES (1u << 19)
+int ks_scan_batch_noalloc(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, const ks_desc *desc,
+                          uint32_t num_series, const ks_params *params, ks_result *out, uint32_t *all_U,
+                          uint64_t all_U_len, void *stream);
+
 /* ------------------------------------------------------------------------
  * Learned proposal (not in the paper: the paper notes that candidate change
  * points could be shortlisted to save work and skips it because its data are

@@ -20,6 +20,7 @@ KS_MAX_K = 2048
 KS_MAX_N = 1 << 24
 KS_CNN_PARAMS = 44993
 KS_FEATURE_MAX_N = 4096
+KS_NOALLOC_MAX_SERIES = 1 << 19
 KS_CNN_TRACE_ACTS = 204
 KS_CNN_TRACE_GRADS = 193
 
@@ -108,6 +109,7 @@ _SIGNATURES = {
     "ks_launch_set": ([_vp, _u32, _u32, _vp], ctypes.c_int),
     "ks_launch_get": ([_vp, _u32, _u32, _vp], ctypes.c_int),
     "ks_autotune": ([_vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
+    "ks_scan_batch_noalloc": ([_vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp, _u64, _vp], ctypes.c_int),
     "ks_model_create": ([_vp, _u64, _vp], ctypes.c_int),
     "ks_model_destroy": ([_vp], ctypes.c_int),
     "ks_model_set_params": ([_vp, _vp], ctypes.c_int),
@@ -224,6 +226,20 @@ def ks_scan_batch(ctx, samples, desc, num_series: int, params: ks_params, out, a
                              _addr(out, 48 * num_series, "out"), _addr(all_U, None, "all_U"), all_U_len,
                              _stream(stream))
     _check(rc, "ks_scan_batch")
+
+
+def ks_scan_batch_noalloc(ctx, samples, desc, num_series: int, params: ks_params, out, all_U=None, stream=None,
+                          num_samples: int | None = None) -> None:
+    """ks_scan_batch with the ordered plan on the library's fixed device scratch (allocates nothing;
+    num_series <= KS_NOALLOC_MAX_SERIES). Calls that overlap in time on one device race."""
+    if num_samples is None:
+        num_samples = samples.numel() * samples.element_size() // 4
+    all_U_len = 0 if all_U is None else (all_U.numel() * all_U.element_size() // 4)
+    rc = lib().ks_scan_batch_noalloc(ctx, _addr(samples, 4 * num_samples, "samples"), num_samples,
+                                     _addr(desc, 24 * num_series, "desc"), num_series, ctypes.byref(params),
+                                     _addr(out, 48 * num_series, "out"), _addr(all_U, None, "all_U"), all_U_len,
+                                     _stream(stream))
+    _check(rc, "ks_scan_batch_noalloc")
 
 
 def ks_launch_set(ctx, max_K: int, num_series: int, mode: int = KS_LAUNCH_ORDERED, chunk_bytes: int = 1 << 20,

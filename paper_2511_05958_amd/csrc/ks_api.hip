@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <new>
 #include <tuple>
@@ -29,7 +30,45 @@ int hip_fail(hipError_t e, const char* what) {
 
 }  // namespace ks_host
 
+// Scratch of ks_scan_batch_noalloc: the ordered plan's header (256 B), then
+// items, per-series moment bases, completion counts and minima laid out for
+// KS_NOALLOC_MAX_SERIES series. Each device holds its own copy for the life
+// of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
 namespace {
+constexpr uint64_t kScratchItems = 256;
+constexpr uint64_t kScratchBase = kScratchItems + 8ull * KS_NOALLOC_MAX_SERIES;
+constexpr uint64_t kScratchDone = kScratchBase + 8ull * KS_NOALLOC_MAX_SERIES;
+constexpr uint64_t kScratchMin = kScratchDone + 4ull * KS_NOALLOC_MAX_SERIES;
+constexpr uint64_t kScratchBytes = kScratchMin + 4ull * KS_NOALLOC_MAX_SERIES;
+static_assert(sizeof(ks::Item) == 8, "item layout");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};  // device address of `scratch` per device
+
+// Resolve the scratch array's address on `device` (made current by the caller), once per device.
+int resolve_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return KS_E_RANGE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return KS_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+  g_scratch[device] = static_cast<unsigned char*>(p);
+  return KS_OK;
+}
+
+unsigned char* scratch_of(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
+}
 
 void free_workspace(ks_ctx* c) {
   (void)hipFree(c->hdr);
@@ -310,6 +349,11 @@ int ks_ctx_create(int device, ks_ctx** out) {
   hipDeviceProp_t prop;
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  {
+    DeviceGuard g(device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    if (int rc = resolve_scratch(device)) return rc;
+  }
   ks_ctx* c = new (std::nothrow) ks_ctx();
   if (!c) return KS_E_NOMEM;
   c->device = device;
@@ -435,6 +479,29 @@ int ks_autotune(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
   if (best) *best = to_launch(cands[bi]);
   if (best_ms) *best_ms = bms;
   return KS_OK;
+}
+
+int ks_scan_batch_noalloc(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, const ks_desc* desc,
+                          uint32_t num_series, const ks_params* params, ks_result* out, uint32_t* all_U,
+                          uint64_t all_U_len, void* stream) {
+  if (!ctx || !params || !out) return KS_E_INVALID;
+  if (int rc = check_params(params)) return rc;
+  if (num_series == 0) return KS_OK;
+  if (!samples || !desc) return KS_E_INVALID;
+  if (num_series > KS_NOALLOC_MAX_SERIES) return KS_E_RANGE;
+  unsigned char* base = scratch_of(ctx->device);
+  if (!base) return KS_E_STATE;  // ks_ctx_create resolves it; not reached for a valid context
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  const uint32_t max_K = params->max_K ? params->max_K : KS_MAX_K;
+  const int kc = k_class(max_K);
+  // the plan kernel rewrites the header, every item and every per-series word
+  // it reads later, so nothing is cleared here
+  ks::Workspace ws{reinterpret_cast<uint32_t*>(base), reinterpret_cast<ks::Item*>(base + kScratchItems),
+                   reinterpret_cast<uint64_t*>(base + kScratchBase), reinterpret_cast<uint32_t*>(base + kScratchDone),
+                   reinterpret_cast<uint32_t*>(base + kScratchMin), nullptr};
+  ScanArgs a{samples, num_samples, desc, num_series, *params, max_K, out, all_U, all_U_len, ks::kNoSplit, ws};
+  return launch_plan(ctx, kc, KS_LAUNCH_ORDERED, a, false, (hipStream_t)stream);
 }
 
 }  // extern "C"
