@@ -1,22 +1,28 @@
-"""Throughput of the exact K-S change-point scan on one MI355X.
+"""Throughput of the exact K-S change-point scan on one MI355X: plain scan and CNN proposal.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5] [--extra c2,c3]
 
 One step = one ks_scan_batch call over the whole batch (eq. 2 reduction,
 K-S at every candidate, choice, significance and p-value for every series),
-with the samples already resident in HBM. Prints ONE JSON line. Besides the
-headline it carries a "learned" leg (propose + exact refine with the trained
-network), a "segment" leg (every level boundary by binary segmentation) and a
-"row_stats" leg (per-row mean, std, min, p50, p95, max), each timed on the
-same batch, a "check" leg (workflow step 3's outlier check and widening, and the
-L2 segment alignment, on the same detections) and a "line_size" leg (the
-cache-line-size scoring on its own synthetic experiments).
+with the samples already resident in HBM. Prints ONE JSON line for the
+headline workload (default c5, the largest configuration: 8192 series x K=1024
+x N=2048, 64 GiB of samples). Besides the plain scan it carries:
+  learned     propose + exact refine with the trained network (and the same
+              refine around the proposal of the method without the network)
+  segment     every level boundary by binary segmentation
+  row_stats   per-row mean, std, min, p50, p95, max
+  check       workflow step 3's outlier check and widening, and the L2 segment
+              alignment, on the same detections
+  line_size   the cache-line-size scoring on its own synthetic experiments
+  workloads   the plain scan and the learned leg on the --extra workloads
+  cpu_baseline  the CPU oracle on a bounded sample of the headline workload,
+              on every core of this process's CPU share and on one core
 
 Workloads (seeded synthetic sweeps, see paper_2511_05958_amd.synth):
   c1  1 series, K=64, N=256            (launch-latency bound, not an HBM number)
-  c2  4096 series, K=256, N=1024        (default; 4 GiB of samples)
+  c2  4096 series, K=256, N=1024        (4 GiB of samples)
   c3  16384 uneven series, K~logU[32,512], N~logU[64,4096]
-  c5  8192 series, K=1024, N=2048       (64 GiB of samples)
+  c5  8192 series, K=1024, N=2048       (default; 64 GiB of samples)
   copy  a plain device-to-device copy of 1 GiB (the reference kernel that
         calibrates the FETCH_SIZE / WRITE_SIZE counters; prints bytes moved)
   ceiling  the achievable HBM read bandwidth: ks_probe_read over 4 GiB, best
@@ -39,65 +45,85 @@ MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511
 MODELS = {"c1": "proposal_r4.ckpt", "c2": "proposal_r4.ckpt", "c3": "proposal_r3.ckpt", "c5": "proposal_r5.ckpt"}
 
 WORKLOADS = {
-    "c1": (1, None, "plain exact scan, 1 series x K=64 x N=256 (one 120->320 cycle change)"),
-    "c2": (2, None, "plain exact scan, 4096 series x K=256 x N=1024 (1-4 planted levels)"),
-    "c3": (3, None, "plain exact scan, 16384 uneven series, K~logU[32,512], N~logU[64,4096], ramps"),
-    "c5": (5, None, "plain exact scan, 8192 series x K=1024 x N=2048 (hard regime)"),
+    "c1": (1, None, "1 series x K=64 x N=256 (one 120->320 cycle change)"),
+    "c2": (2, None, "4096 series x K=256 x N=1024 (1-4 planted levels)"),
+    "c3": (3, None, "16384 uneven series, K~logU[32,512], N~logU[64,4096], 0-4 changes with ramps"),
+    "c5": (5, None, "8192 series x K=1024 x N=2048, hard regime (adjacent level ratios 1.05-1.2, Pareto tails, "
+                    "5% outliers)"),
 }
+METRIC = "KS change-point series/s at 1 GPU (plain vs CNN-proposal), % HBM roofline"
 
 
-def cpu_baseline(batch, samples_dev, threads: int, target_s: float = 10.0, max_bytes: int = 2 << 30) -> dict:
-    """The CPU oracle, as it stands, on a bounded sample of the same workload.
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    The first series of the batch (already in HBM) are copied to the host; a
-    64-series probe estimates the oracle's rate, then enough further series
-    for about target_s seconds of oracle work (at most max_bytes of samples,
-    at most the whole batch) are timed. When that bounded sample takes less
-    than target_s, the oracle runs over it again until about target_s of work
-    is timed (the rate counts every pass)."""
+
+def cpu_baseline(batch, samples_dev, sample_series: int = 512, target_s: float = 8.0) -> dict:
+    """The CPU oracle, as it stands, on a bounded sample of the headline workload: the
+    first `sample_series` series of the batch, copied from HBM (the generator is keyed by
+    series id and bit-identical on host and device, so these are exactly the series the
+    host generator would regenerate). Timed on every core of this process's CPU share
+    (os.sched_getaffinity, capped at OMP_NUM_THREADS when that is set) and on one core;
+    one core takes as many of those series as fit in about target_s seconds. Rates are
+    series/s, so they scale to the whole batch directly (batch seconds = series / rate)."""
     import numpy as np
 
     import oracle as O
 
     sp = batch.specs
+    count = max(1, min(sample_series, batch.num_series))
     ends = sp["offset"].astype(np.int64) + sp["K"].astype(np.int64) * sp["N"].astype(np.int64)
-    fit = int(np.searchsorted(ends, max_bytes // 4, side="right"))
-    limit = max(1, min(batch.num_series, fit))
+    x = samples_dev[: int(ends[count - 1])].cpu().numpy().view(np.uint32)
+    affinity = len(os.sched_getaffinity(0))
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    cores = min(affinity, share) if share > 0 else affinity
 
-    def host_prefix(count):
-        return samples_dev[: int(ends[count - 1])].cpu().numpy().view(np.uint32)
-
-    probe = min(limit, 64)
-    x = host_prefix(probe)
-    t0 = time.perf_counter()
-    O.scan_batch(x, sp["offset"][:probe], sp["K"][:probe], sp["N"][:probe], threads=threads)
-    rate = probe / max(time.perf_counter() - t0, 1e-9)
-    count = int(min(limit, max(probe, rate * target_s)))
-    x = host_prefix(count)
-    passes, dt = 0, 0.0
-    while passes == 0 or (dt < target_s and passes < 100):
+    def timed_run(n, threads):
         t0 = time.perf_counter()
-        O.scan_batch(x, sp["offset"][:count], sp["K"][:count], sp["N"][:count], threads=threads)
-        dt += time.perf_counter() - t0
-        passes += 1
+        O.scan_batch(x, sp["offset"][:n], sp["K"][:n], sp["N"][:n], threads=threads)
+        return time.perf_counter() - t0
+
+    dt_all = timed_run(count, cores)
+    probe = min(count, 8)
+    rate1 = probe / timed_run(probe, 1)
+    n1 = int(min(count, max(probe, rate1 * target_s)))
+    dt1 = timed_run(n1, 1)
+    gib = 4 * int(ends[count - 1]) / 2**30
+    full_s = batch.num_series / (count / dt_all)
     return {
-        "value": passes * count / dt,
+        "value": count / dt_all,
         "unit": "series/s",
-        "cores": threads,
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"first {count} of {batch.num_series} series of the same batch "
-                  f"({4 * int(ends[count - 1]) / 2**30:.2f} GiB) x {passes} passes, {threads} threads, {dt:.2f} s",
+        "sample": f"series 0..{count - 1} of the {batch.num_series}-series batch ({gib:.2f} GiB, copied from HBM; "
+                  f"bit-identical to regenerating them from their Philox streams), {cores} threads, {dt_all:.2f} s; "
+                  f"scaled to the whole batch: {full_s:.1f} s",
+        "one_core": {"value": n1 / dt1, "unit": "series/s", "cores": 1, "series": n1, "seconds": dt1,
+                     "batch_seconds_scaled": batch.num_series / (n1 / dt1)},
+        "nproc": os.cpu_count(),
+        "affinity_cores": affinity,
+        "cpu_model": cpu_model(),
     }
 
 
-def learned_leg(args, ctx, batch, samples, desc, out_plain, prm, stream, res_plain, plain_value) -> dict:
-    """Propose + exact refine on the same batch, timed like the plain step; agreement with the plain scan."""
+def learned_leg(args, ctx, batch, samples, desc, prm, stream, res_plain, plain_value, model_path) -> dict:
+    """Propose + exact refine on the same batch, timed like the plain step; agreement with the
+    plain scan and fallback rate at the model's calibrated tau. Beside it, the same refine around
+    the proposal of the method without the network (ks_propose with no model: the largest jump
+    of the per-row median, always refined), its agreement and series/s."""
     import numpy as np
     import torch
 
     import paper_2511_05958_amd as P
 
-    rep_path = os.path.splitext(args.model)[0] + ".json"
+    rep_path = os.path.splitext(model_path)[0] + ".json"
     with open(rep_path) as f:
         rep = json.load(f)
     n = batch.num_series
@@ -106,32 +132,37 @@ def learned_leg(args, ctx, batch, samples, desc, out_plain, prm, stream, res_pla
     lp.w = 8
     lp.tau = float(rep["tau"])
     model = P.Model(ctx, seed=0)
-    P.ks_model_load(model.handle, args.model)
+    P.ks_model_load(model.handle, model_path)
     prop = torch.empty(n, dtype=torch.int32, device="cuda")
     conf = torch.empty(n, dtype=torch.float32, device="cuda")
     out = P.empty_results(n)
 
-    def step():
-        P.ks_propose(ctx.handle, model.handle, samples, desc, n, lp, prop, conf, stream=stream)
-        P.ks_refine(ctx.handle, desc, n, batch.total_elems, prop, conf, lp, out, stream=stream)
+    def run(handle):
+        def step():
+            P.ks_propose(ctx.handle, handle, samples, desc, n, lp, prop, conf, stream=stream)
+            P.ks_refine(ctx.handle, desc, n, batch.total_elems, prop, conf, lp, out, stream=stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall_ms = (time.perf_counter() - t0) / args.steps * 1e3
-    ev_ms = e0.elapsed_time(e1) / args.steps
-    r = P.results_to_numpy(out)
-    agree = (r["cp"] == res_plain["cp"]) & (r["U"] == res_plain["U"])
-    value = n / (wall_ms / 1e3)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        r = P.results_to_numpy(out)
+        agree = (r["cp"] == res_plain["cp"]) & (r["U"] == res_plain["U"])
+        return wall_ms, e0.elapsed_time(e1) / args.steps, r, agree
+
+    wall_ms, ev_ms, r, agree = run(model.handle)
+    t_ms, _, _, t_agree = run(None)
     model.close()
+    value = n / (wall_ms / 1e3)
+    cal = rep.get("calibration", {})
     return {
         "value": value,
         "unit": "series/s",
@@ -142,8 +173,14 @@ def learned_leg(args, ctx, batch, samples, desc, out_plain, prm, stream, res_pla
         "fallback_rate": float(np.mean((r["flags"] & P.KS_FALLBACK) != 0)),
         "w": lp.w,
         "tau": lp.tau,
+        "tau_calibration": {"series": cal.get("series", rep.get("val_series")),
+                            "target": cal.get("target", rep.get("target")),
+                            "held_out_agreement": cal.get("agreement_at_tau", rep.get("val_agreement_at_tau"))},
         "hbm_GBps_whole_step": (batch.sample_bytes + 48 * n) / (ev_ms / 1e3) / 1e9,
-        "model": os.path.basename(args.model),
+        "model": os.path.basename(model_path),
+        "without_network": {"value": n / (t_ms / 1e3), "unit": "series/s", "ms_per_step": t_ms,
+                            "agreement": float(t_agree.mean()), "fallback_rate": 0.0,
+                            "proposal": "largest jump of the per-row median, always refined"},
     }
 
 
@@ -409,67 +446,31 @@ def read_ceiling(args) -> int:
     return 0
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["copy", "ceiling"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--launch", default="autotune",
-                    choices=["autotune", "default", "grid", "ordered", "persistent", "persistent-direct"],
-                    help="launch plan: autotune (time the candidates first, untimed), the library default, "
-                         "one workgroup per series, largest-first ordered grid, persistent queue (hipGraph), "
-                         "persistent queue with direct launches")
-    ap.add_argument("--chunk", type=int, default=1 << 20, help="split size of the persistent plan (bytes)")
-    ap.add_argument("--model", default=None,
-                    help="trained proposal network; its .json report holds tau (learned mode is skipped if absent). "
-                         "Default: the network trained on the workload's own shapes (series ids disjoint from the "
-                         "benchmark batch)")
-    ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--no-segment", action="store_true", help="skip the binary-segmentation leg")
-    ap.add_argument("--no-ceiling", action="store_true", help="skip the measured read-ceiling probe")
-    ap.add_argument("--no-stats", action="store_true", help="skip the per-row statistics leg")
-    ap.add_argument("--no-check", action="store_true",
-                    help="skip the workflow-check legs (outlier check, L2 alignment, cache-line size)")
-    args = ap.parse_args()
-    if args.model is None:
-        args.model = os.path.join(MODEL_DIR, MODELS.get(args.workload, "proposal_r4.ckpt"))
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        return 2
-
+def plain_scan(args, ctx, key, stream, launch="autotune"):
+    """Generate workload `key` in HBM and time the plain exact scan on it: (record, state)."""
     import numpy as np
     import torch
 
     import paper_2511_05958_amd as P
     from paper_2511_05958_amd import synth as S
 
-    if args.workload == "copy":
-        return copy_calibration(args)
-    if args.workload == "ceiling":
-        return read_ceiling(args)
-    recipe, count, label = WORKLOADS[args.workload]
+    recipe, count, label = WORKLOADS[key]
     batch = S.make_batch(recipe, num_series=count)
     n = batch.num_series
-    dev = torch.device("cuda:0")
-    samples = torch.empty(batch.total_elems, dtype=torch.int32, device=dev)
+    samples = torch.empty(batch.total_elems, dtype=torch.int32, device="cuda")
     S.fill_device(batch, samples.data_ptr(), batch.total_elems)
-    desc = P.to_device(P.make_desc(batch.specs["offset"], batch.specs["K"], batch.specs["N"]), dev)
-    out = P.empty_results(n, dev)
+    desc = P.to_device(P.make_desc(batch.specs["offset"], batch.specs["K"], batch.specs["N"]))
+    out = P.empty_results(n)
     prm = P.ks_params_init(0.05)
     prm.max_K = int(batch.specs["K"].max())
-    ctx = P.Context(0)
-    stream = torch.cuda.current_stream(dev)
     chosen = None
-    if args.launch == "autotune":
+    if launch == "autotune":
         best, _ = P.ks_autotune(ctx.handle, samples, desc, n, prm, out, stream=stream)
         chosen = {"mode": best.mode, "chunk_bytes": best.chunk_bytes, "graph": best.graph}
-    elif args.launch != "default":
+    elif launch != "default":
         cfg = {"grid": (P.KS_LAUNCH_GRID, args.chunk, 0), "ordered": (P.KS_LAUNCH_ORDERED, args.chunk, 1),
                "persistent": (P.KS_LAUNCH_PERSISTENT, args.chunk, 1),
-               "persistent-direct": (P.KS_LAUNCH_PERSISTENT, args.chunk, 0)}[args.launch]
+               "persistent-direct": (P.KS_LAUNCH_PERSISTENT, args.chunk, 0)}[launch]
         P.ks_launch_set(ctx.handle, prm.max_K, n, *cfg)
     if chosen is None:
         c = P.ks_launch_get(ctx.handle, prm.max_K, n)
@@ -493,25 +494,14 @@ def main() -> int:
     kern_ms = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
     avg_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
     ms_per_step = wall / args.steps * 1e3
-
     res = P.results_to_numpy(out)
-    bad = int(np.count_nonzero(res["flags"] & (P.KS_BAD_SHAPE | P.KS_OUT_OF_RANGE)))
     bytes_per_launch = batch.sample_bytes + 48 * n
     kernel_name = "ks::scan_persistent" if chosen["mode"] == P.KS_LAUNCH_PERSISTENT else "ks::scan_kernel"
     achieved = bytes_per_launch / avg_kern_s / 1e9
-    line = {
-        "metric": "KS change-point series/s at 1 GPU (plain exact scan), % HBM roofline",
+    rec = {
         "value": n / (ms_per_step / 1e3),
         "unit": "series/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
         "config": {
             "workload": label,
             "series": n,
@@ -520,7 +510,7 @@ def main() -> int:
             "alpha": prm.alpha,
             "launch": chosen,
             "significant": int(np.count_nonzero(res["flags"] & P.KS_SIGNIFICANT)),
-            "flagged_bad": bad,
+            "flagged_bad": int(np.count_nonzero(res["flags"] & (P.KS_BAD_SHAPE | P.KS_OUT_OF_RANGE))),
         },
         "roofline": {
             "bound": "hbm",
@@ -528,11 +518,80 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": recorded_traffic(kernel_name, args.workload),
+            "traffic": recorded_traffic(kernel_name, key),
             "kernel": kernel_name,
             "kernel_ms": avg_kern_s * 1e3,
         },
     }
+    return rec, (batch, samples, desc, out, prm, res)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["copy", "ceiling"])
+    ap.add_argument("--extra", default="c2,c3",
+                    help="comma-separated workloads whose plain scan and learned leg are added under 'workloads' "
+                         "('' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--launch", default="autotune",
+                    choices=["autotune", "default", "grid", "ordered", "persistent", "persistent-direct"],
+                    help="launch plan: autotune (time the candidates first, untimed), the library default, "
+                         "one workgroup per series, largest-first ordered grid, persistent queue (hipGraph), "
+                         "persistent queue with direct launches")
+    ap.add_argument("--chunk", type=int, default=1 << 20, help="split size of the persistent plan (bytes)")
+    ap.add_argument("--model", default=None,
+                    help="trained proposal network for the headline workload; its .json report holds tau (the "
+                         "learned leg is skipped if absent). Default: the network trained on the workload's own "
+                         "shapes (series ids disjoint from the benchmark batch)")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-segment", action="store_true", help="skip the binary-segmentation leg")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the measured read-ceiling probe")
+    ap.add_argument("--no-stats", action="store_true", help="skip the per-row statistics leg")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the workflow-check legs (outlier check, L2 alignment, cache-line size)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only (one GPU's share of a batch sharded by "
+                                   "series); --gpus must be 1", "n_gpus": args.gpus}))
+        return 2
+
+    import torch
+
+    import paper_2511_05958_amd as P
+
+    if args.workload == "copy":
+        return copy_calibration(args)
+    if args.workload == "ceiling":
+        return read_ceiling(args)
+    extras = [w for w in args.extra.split(",") if w and w != args.workload]
+    for w in extras:
+        if w not in WORKLOADS:
+            raise SystemExit(f"unknown workload {w}")
+    model_path = args.model or os.path.join(MODEL_DIR, MODELS.get(args.workload, "proposal_r4.ckpt"))
+    ctx = P.Context(0)
+    stream = torch.cuda.current_stream()
+    rec, (batch, samples, desc, out, prm, res) = plain_scan(args, ctx, args.workload, stream, args.launch)
+    n = batch.num_series
+    line = {
+        "metric": METRIC,
+        "value": rec["value"],
+        "unit": "series/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": rec["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": rec["config"],
+        "roofline": rec["roofline"],
+    }
+    achieved = rec["roofline"]["achieved"]
     if not args.no_ceiling:
         # the read bandwidth a plain 16-byte-load kernel reaches on this device (best of three
         # launch shapes of ks_probe_read; the full sweep is --workload ceiling)
@@ -540,8 +599,8 @@ def main() -> int:
         ceil_gbps = max(q["GBps"] for q in pts)
         line["roofline"]["measured_read_ceiling_GBps"] = ceil_gbps
         line["roofline"]["frac_of_measured_ceiling"] = achieved / ceil_gbps
-    if not args.no_learned and os.path.exists(args.model) and batch.specs["N"].max() <= P.KS_FEATURE_MAX_N:
-        line["learned"] = learned_leg(args, ctx, batch, samples, desc, out, prm, stream, res, n / (ms_per_step / 1e3))
+    if not args.no_learned and os.path.exists(model_path) and batch.specs["N"].max() <= P.KS_FEATURE_MAX_N:
+        line["learned"] = learned_leg(args, ctx, batch, samples, desc, prm, stream, res, rec["value"], model_path)
     if not args.no_segment:
         line["segment"] = segment_leg(args, ctx, batch, samples, desc, prm, stream)
     if not args.no_stats and batch.specs["N"].max() <= P.KS_FEATURE_MAX_N:
@@ -549,12 +608,23 @@ def main() -> int:
         if not args.no_check:
             line["check"] = check_leg(args, ctx, batch, desc, prm, out, stats_out, line["row_stats"]["ms_per_step"],
                                       stream)
-            del stats_out
+        del stats_out
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(batch, samples)
+    del samples, desc, out
+    torch.cuda.empty_cache()
     if not args.no_check:
         line["line_size"] = line_leg(args, ctx, stream)
-    if not args.no_cpu_baseline:
-        threads = min(16, len(os.sched_getaffinity(0)))
-        line["cpu_baseline"] = cpu_baseline(batch, samples, threads)
+    if extras:
+        line["workloads"] = {}
+    for w in extras:
+        r, (b, s_, d_, o_, p_, res_) = plain_scan(args, ctx, w, stream, args.launch)
+        mp = os.path.join(MODEL_DIR, MODELS.get(w, "proposal_r4.ckpt"))
+        if not args.no_learned and os.path.exists(mp) and b.specs["N"].max() <= P.KS_FEATURE_MAX_N:
+            r["learned"] = learned_leg(args, ctx, b, s_, d_, p_, stream, res_, r["value"], mp)
+        line["workloads"][w] = r
+        del s_, d_, o_
+        torch.cuda.empty_cache()
     ctx.close()
     print(json.dumps(line), flush=True)
     return 0
