@@ -11,27 +11,43 @@
 namespace ks {
 
 // ------------------------------------------------------------------ deciles
-// Nine order statistics of one row, found by one wave with no block barrier:
-// an MSD radix select over the keys r - row minimum. Level 0 histograms the
-// top kSelW0 bits of every key; each later level histograms the next kSelW
-// bits of only the keys that share a target's prefix so far. Those keys form
-// at most nine groups (one per distinct prefix among the targets), numbered in
-// target order. After each level every key is rewritten in place as
-// (group << s) | (its s low bits), s the bits still unresolved, with group
-// kSelNone for keys outside every group, so the next level's bin is the key
-// shifted right by the next s. Histograms are LDS counters per (group, digit)
-// bin; keys whose bin lies past the live groups issue no LDS access (such
-// keys would pile onto a few addresses and serialise the atomics).
+// Up to nine order statistics of one row, found by one wave with no block
+// barrier, over the keys r - row minimum.
+//
+// Window level. One histogram pass with one bin per key value below
+// kSelWin - 1 and a last bin for every larger key: order statistics of latency
+// rows sit in the bulk of the row, within a few hundred cycles of its minimum,
+// so this single pass resolves them exactly (a target's value is its bin).
+// The bins' counts are summed per lane (16 bins each), a wave scan gives each
+// lane's base, a ballot per target finds the lane whose bins hold its rank,
+// and that lane's 16 bins give the bin.
+//
+// Radix levels, for targets that fall into the last bin (and for rows whose
+// keys may equal the empty-slot sentinel): an MSD radix select over the keys
+// of that bin. Level 0 histograms the top kSelW0 bits of every key; each later
+// level histograms the next kSelW bits of only the keys that share a target's
+// prefix so far. Those keys form at most nine groups (one per distinct prefix
+// among the targets), numbered in target order. After each level every key is
+// rewritten in place as (group << s) | (its s low bits), s the bits still
+// unresolved, with group kSelNone for keys outside every group, so the next
+// level's bin is the key shifted right by the next s. Histograms are LDS
+// counters per (group, digit) bin; keys whose bin lies past the live groups
+// issue no LDS access (such keys would pile onto a few addresses and serialise
+// the atomics).
 
+constexpr uint32_t kSelWin = 1024; // bins of the window level: keys 0 .. 1022 one each, 1023 the rest
 constexpr uint32_t kSelW0 = 10;    // bits of the level-0 digit (1024 bins fit the histogram)
 constexpr uint32_t kSelW = 7;      // bits of every later digit
 constexpr uint32_t kSelNone = 9;   // group of keys outside every target's prefix
+constexpr uint32_t kSelEmpty = 0xffffffffu;  // key of a slot without a sample
 
 struct __align__(16) SelLds {
   uint32_t hist[(kSelNone + 1) << kSelW];  // bin counts, then exclusive prefixes
   uint8_t tab[(kSelNone + 1) << kSelW];    // bin -> group at the next level
 };
 static_assert((1u << kSelW0) <= ((kSelNone + 1) << kSelW), "level-0 bins fit the histogram");
+static_assert(kSelWin == 16u * kWave && kSelWin + kWave <= ((kSelNone + 1) << kSelW),
+              "16 window bins per lane and a spare word per lane fit");
 static_assert((((kSelNone << kSelW) + 255u) & ~255u) <= ((kSelNone + 1) << kSelW), "padded live bins fit");
 
 // LDS accesses of one wave are performed in order; this keeps the compiler
@@ -74,17 +90,16 @@ struct DecileRanks {
   __device__ static uint32_t rank(uint32_t j, uint32_t N) { return (uint32_t)(((uint64_t)(j + 1) * (N - 1)) / 10u); }
 };
 
-// k[]: this lane's keys (values - row minimum; slots without a sample hold
-// 0xffffffff, which lies past every level-0 bin unless b = 32, and then sorts
-// at or after the row maximum), b >= 1 the bit length of the row's range; the
-// keys are consumed. Lane j < RANKS::kCount returns the key of rank
-// RANKS::rank(j, N).
-template <int V, class RANKS>
-__device__ __forceinline__ uint32_t wave_select(SelLds& L, uint32_t (&k)[V], uint32_t b, uint32_t N,
-                                                uint32_t lane) {
-  static_assert(RANKS::kCount >= 1 && RANKS::kCount <= kSelNone, "at most nine targets");
-  const bool tl = lane < RANKS::kCount;
-  uint32_t R = tl ? RANKS::rank(lane, N) : 0u;  // rank within the group
+// Radix levels. k[]: this lane's keys, every one below 2^b (b >= 1), empty
+// slots holding kSelEmpty, which lies past every level-0 bin unless b = 32,
+// and then sorts at or after every key; the keys are consumed. Lanes with tl
+// (at most kSelNone of them, consecutive lanes, ranks R non-decreasing with
+// the lane) return the key of rank R.
+template <int V>
+__device__ __forceinline__ uint32_t radix_select(SelLds& L, uint32_t (&k)[V], uint32_t b, uint32_t R, bool tl,
+                                                 uint32_t lane) {
+  const uint64_t tm = ballot(tl);
+  const uint32_t first = tm ? (uint32_t)__builtin_ctzll(tm) : 0u;  // participating lanes: first, first + 1, ...
   uint32_t tg = 0, key = 0, G = 1, sprev = b, wmax = kSelW0;
 #pragma unroll 1
   for (;;) {
@@ -120,7 +135,7 @@ __device__ __forceinline__ uint32_t wave_select(SelLds& L, uint32_t (&k)[V], uin
     if (s == 0) break;
     // groups of the next level: the targets' distinct bins, in target order
     const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
-    const bool fresh = tl && (lane == 0 || x != prev);
+    const bool fresh = tl && (lane == first || x != prev);
     const uint64_t m = ballot(fresh);
     const uint32_t id = mbcnt(m) - (fresh ? 0u : 1u);
     const uint32_t words = live / 4u;
@@ -149,6 +164,83 @@ __device__ __forceinline__ uint32_t wave_select(SelLds& L, uint32_t (&k)[V], uin
     wmax = kSelW;
   }
   return key;
+}
+
+// k[]: this lane's keys (values - row minimum, empty slots kSelEmpty), b >= 1
+// the bit length of the row's range; the keys are consumed. Lane
+// j < RANKS::kCount returns the key of rank RANKS::rank(j, N), N the number of
+// keys in the wave.
+template <int V, class RANKS>
+__device__ __forceinline__ uint32_t wave_select(SelLds& L, uint32_t (&k)[V], uint32_t b, uint32_t N,
+                                                uint32_t lane) {
+  static_assert(RANKS::kCount >= 1 && RANKS::kCount <= kSelNone, "at most nine targets");
+  const bool tl = lane < RANKS::kCount;
+  const uint32_t R = tl ? RANKS::rank(lane, N) : 0u;
+  if (b >= 32) return radix_select<V>(L, k, b, R, tl, lane);  // a key may equal the sentinel
+  // window level: bin min(key, kSelWin - 1); empty slots count in a spare word
+  // of their own lane past the window (kSelWin + lane, never read), so that the
+  // row's empty tail slots do not pile onto one address
+  u32x4* hv = reinterpret_cast<u32x4*>(L.hist);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) hv[lane * 4 + i] = u32x4{0u, 0u, 0u, 0u};
+  wave_lds_sync();
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const uint32_t x = k[e];
+    atomicAdd(&L.hist[x == kSelEmpty ? kSelWin + lane : min(x, kSelWin - 1u)], 1u);
+    if (V > 17 && e % 17 == 16) __builtin_amdgcn_sched_barrier(0);  // bounds the addresses in flight
+  }
+  wave_lds_sync();
+  // lane l holds bins 16 l .. 16 l + 15: their total, and the wave scan of the totals
+  uint32_t t = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const u32x4 q = hv[lane * 4 + i];
+    t += q.x + q.y + q.z + q.w;
+  }
+  const uint32_t incl = wave_incl_scan(t);
+  // the lane whose bins hold each target's rank: the first whose inclusive count exceeds it
+  uint32_t owner = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < RANKS::kCount; ++j) {
+    const uint32_t Rj = (uint32_t)__builtin_amdgcn_readlane((int)R, (int)j);
+    const uint64_t m = ballot(incl > Rj);  // not empty: Rj < N, the total
+    const uint32_t o = m ? (uint32_t)__builtin_ctzll(m) : kWave - 1u;
+    if (lane == j) owner = o;
+  }
+  const uint32_t below = (uint32_t)__shfl((int)(incl - t), (int)owner);  // keys in the owner's lower lanes
+  uint32_t key = 0, r = 0;
+  bool last = false;
+  if (tl) {
+    r = R - below;  // rank within the owner's 16 bins
+    uint32_t bin = owner * 16u;
+    bool found = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const u32x4 q = hv[owner * 4 + i];
+      const uint32_t c[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (!found) {
+          if (r < c[e]) {
+            found = true;
+          } else {
+            r -= c[e];
+            ++bin;
+          }
+        }
+      }
+    }
+    key = bin;
+    last = bin == kSelWin - 1u;  // keys >= kSelWin - 1: rank r among them
+  }
+  wave_lds_sync();
+  if (ballot(last) == 0) return key;
+  // targets in the last bin: radix levels over its keys, relative to its first value
+#pragma unroll
+  for (int e = 0; e < V; ++e) k[e] = (k[e] != kSelEmpty && k[e] >= kSelWin - 1u) ? k[e] - (kSelWin - 1u) : kSelEmpty;
+  const uint32_t kk = radix_select<V>(L, k, b, r, last, lane);
+  return last ? kk + (kSelWin - 1u) : key;
 }
 
 // Batches of one row (NB of them; batches past the row's last are empty).
