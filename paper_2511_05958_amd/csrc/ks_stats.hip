@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void row_stats_kernel(const uint32_t* __restri
     ks::load_row<NB>(cur, samples, d.offset + (uint64_t)i * N, N, lane);
     uint64_t s1, s2;
     uint32_t s2h, rmax, sel_x;
-    const uint32_t rmin = ks::row_pass<NB, StatRanks>(L, cur, N, lane, s1, s2, s2h, rmax, sel_x);
+    const uint32_t rmin = ks::row_pass<NB, StatRanks, true>(L, cur, N, lane, s1, s2, s2h, rmax, sel_x);
     const uint32_t p95 = (uint32_t)__builtin_amdgcn_readlane((int)sel_x, 1);
     if (lane == 0) {
       const u128 S2 = ((u128)s2h << 64) | s2;
