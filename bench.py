@@ -52,6 +52,8 @@ WORKLOADS = {
                     "5% outliers)"),
 }
 METRIC = "KS change-point series/s at 1 GPU (plain vs CNN-proposal), % HBM roofline"
+# scan-kernel variants of ks_launch.variant (include/ks.h): workgroup threads, radix bits, walk slots (0: share)
+SCAN_VARIANTS = [(256, 4, 0), (128, 4, 0), (512, 4, 0), (256, 8, 0), (256, 4, 1), (256, 4, 2)]
 
 
 def cpu_model() -> str:
@@ -356,7 +358,7 @@ def line_leg(args, ctx, stream, num_exp: int = 1024, J: int = 16, A: int = 32, N
 # ctypes layouts' itemsize checks.)
 SCAN_SOURCES = ["paper_2511_05958_amd/csrc/ks_wave.hpp", "paper_2511_05958_amd/csrc/ks_scan.hpp",
                 "paper_2511_05958_amd/csrc/ks_persist.hpp", "paper_2511_05958_amd/csrc/ks_ctx.hpp",
-                "paper_2511_05958_amd/csrc/ks_api.hip"]
+                "paper_2511_05958_amd/csrc/ks_api.hip", "paper_2511_05958_amd/csrc/ks_scan_variants.hip"]
 TRAFFIC_FILE = os.path.join("profiles", "hbm_traffic.txt")
 
 
@@ -463,18 +465,21 @@ def plain_scan(args, ctx, key, stream, launch="autotune"):
     out = P.empty_results(n)
     prm = P.ks_params_init(0.05)
     prm.max_K = int(batch.specs["K"].max())
-    chosen = None
+    tune_ms = None
     if launch == "autotune":
-        best, _ = P.ks_autotune(ctx.handle, samples, desc, n, prm, out, stream=stream)
-        chosen = {"mode": best.mode, "chunk_bytes": best.chunk_bytes, "graph": best.graph}
+        t0 = time.perf_counter()
+        P.ks_autotune(ctx.handle, samples, desc, n, prm, out, stream=stream)
+        tune_ms = (time.perf_counter() - t0) * 1e3
     elif launch != "default":
         cfg = {"grid": (P.KS_LAUNCH_GRID, args.chunk, 0), "ordered": (P.KS_LAUNCH_ORDERED, args.chunk, 1),
                "persistent": (P.KS_LAUNCH_PERSISTENT, args.chunk, 1),
                "persistent-direct": (P.KS_LAUNCH_PERSISTENT, args.chunk, 0)}[launch]
-        P.ks_launch_set(ctx.handle, prm.max_K, n, *cfg)
-    if chosen is None:
-        c = P.ks_launch_get(ctx.handle, prm.max_K, n)
-        chosen = {"mode": c.mode, "chunk_bytes": c.chunk_bytes, "graph": c.graph}
+        P.ks_launch_set(ctx.handle, prm.max_K, n, *cfg, variant=args.variant)
+    c = P.ks_launch_get(ctx.handle, prm.max_K, n)
+    nt, rb, gm = SCAN_VARIANTS[c.variant]
+    chosen = {"mode": ["grid", "persistent", "ordered"][c.mode], "chunk_bytes": c.chunk_bytes, "graph": c.graph,
+              "variant": c.variant, "workgroup_threads": nt, "radix_bits": rb,
+              "walk_slots_per_wave": gm or "share", "autotune_ms": tune_ms}
 
     def step():
         P.ks_scan_batch(ctx.handle, samples, desc, n, prm, out, stream=stream)
@@ -496,7 +501,7 @@ def plain_scan(args, ctx, key, stream, launch="autotune"):
     ms_per_step = wall / args.steps * 1e3
     res = P.results_to_numpy(out)
     bytes_per_launch = batch.sample_bytes + 48 * n
-    kernel_name = "ks::scan_persistent" if chosen["mode"] == P.KS_LAUNCH_PERSISTENT else "ks::scan_kernel"
+    kernel_name = "ks::scan_persistent" if c.mode == P.KS_LAUNCH_PERSISTENT else "ks::scan_kernel"
     achieved = bytes_per_launch / avg_kern_s / 1e9
     rec = {
         "value": n / (ms_per_step / 1e3),
@@ -542,6 +547,7 @@ def main() -> int:
                          "one workgroup per series, largest-first ordered grid, persistent queue (hipGraph), "
                          "persistent queue with direct launches")
     ap.add_argument("--chunk", type=int, default=1 << 20, help="split size of the persistent plan (bytes)")
+    ap.add_argument("--variant", type=int, default=0, help="scan-kernel variant with a fixed --launch plan")
     ap.add_argument("--model", default=None,
                     help="trained proposal network for the headline workload; its .json report holds tau (the "
                          "learned leg is skipped if absent). Default: the network trained on the workload's own "

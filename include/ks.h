@@ -182,30 +182,38 @@ int ks_scan_batch(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, co
  *                with more sample bytes are cut into row ranges of about
  *                this size (at most 64 per series)
  *   graph        1: replay a planned launch from a cached hipGraph;
- *                0: launch its kernels directly */
+ *                0: launch its kernels directly
+ *   variant      scan-kernel variant, 0 .. KS_SCAN_VARIANTS - 1 (tile = the
+ *                workgroup size, radix digit bits of the key sort, walk
+ *                window = candidate slots of 64 a wave walks at once):
+ *                0 {256 threads, 4 bits, whole share}, 1 {128, 4, share},
+ *                2 {512, 4, share}, 3 {256, 8, share}, 4 {256, 4, one slot},
+ *                5 {256, 4, two slots}. Every variant gives the same results. */
+#define KS_SCAN_VARIANTS 6u
 typedef struct ks_launch {
   uint32_t mode;
   uint32_t chunk_bytes;
   uint32_t graph;
-  uint32_t pad;
+  uint32_t variant;
 } ks_launch;
 
 /* Record (ks_launch_set) or read (ks_launch_get) the plan ks_scan_batch uses
  * for batches with this max_K class and num_series; without a record the
- * default is {KS_LAUNCH_ORDERED, 1 MiB, 1}. KS_E_INVALID / KS_E_RANGE on bad
- * values. */
+ * default is {KS_LAUNCH_ORDERED, 1 MiB, 1, 0}. KS_E_INVALID / KS_E_RANGE on
+ * bad values. */
 int ks_launch_set(ks_ctx *ctx, uint32_t max_K, uint32_t num_series, const ks_launch *cfg);
 int ks_launch_get(ks_ctx *ctx, uint32_t max_K, uint32_t num_series, ks_launch *cfg);
 
-/* Autotuner: time every candidate plan (grid; ordered grid from a hipGraph
- * and direct; persistent with chunk_bytes 1, 4, 16 MiB, from a hipGraph and
- * direct) on this
- * very batch with HIP events on `stream` (one warm-up, best of three), record
- * the fastest with ks_launch_set, and return it in *best (nullable) and its
- * time in *best_ms (nullable). Blocks until done; writes `out`. When the
- * environment variable KS_TUNE_CACHE names a file, the choice is appended to
- * it, and ks_ctx_create loads the records written for the same device
- * (architecture and CU count). Arguments as ks_scan_batch. */
+/* Autotuner, on this very batch with HIP events on `stream` (one warm-up,
+ * best of three per candidate): every scan-kernel variant (tile, sort radix,
+ * walk window) under every launch plan (grid; ordered grid from a hipGraph and
+ * direct; persistent with chunk_bytes 1, 4, 16 MiB, from a hipGraph and
+ * direct), 6 x 9 candidates. Records the fastest
+ * with ks_launch_set and returns it in *best (nullable) and its time in
+ * *best_ms (nullable). Blocks until done; writes `out`. When the environment
+ * variable KS_TUNE_CACHE names a file, the choice is appended to it, and
+ * ks_ctx_create loads the records written for the same device (architecture
+ * and CU count). Arguments as ks_scan_batch. */
 int ks_autotune(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, const ks_desc *desc,
                 uint32_t num_series, const ks_params *params, ks_result *out, void *stream, ks_launch *best,
                 float *best_ms);
@@ -217,7 +225,8 @@ int ks_autotune(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, cons
  * instead of the context's workspace. It allocates nothing and launches the
  * plan's two kernels directly (no hipGraph).
  *   Arguments, results and per-series flags as ks_scan_batch; params->opts
- *   is checked but the launch plan is always the ordered grid.
+ *   is checked but the launch plan is always the ordered grid (with the
+ *   scan-kernel variant recorded for this batch shape, else variant 0).
  *   num_series <= KS_NOALLOC_MAX_SERIES, else KS_E_RANGE (nothing launched).
  *   Scratch: 256 + 24 * KS_NOALLOC_MAX_SERIES bytes (12 MiB + 256 B) per
  *   device, held until the process ends; ks_ctx_create resolves its address

@@ -81,9 +81,12 @@ KS_LAUNCH_PERSISTENT = 1
 KS_LAUNCH_ORDERED = 2
 
 
+KS_SCAN_VARIANTS = 6
+
+
 class ks_launch(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32), ("graph", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("variant", ctypes.c_uint32)]
 
 
 class KsError(RuntimeError):
@@ -243,8 +246,8 @@ def ks_scan_batch_noalloc(ctx, samples, desc, num_series: int, params: ks_params
 
 
 def ks_launch_set(ctx, max_K: int, num_series: int, mode: int = KS_LAUNCH_ORDERED, chunk_bytes: int = 1 << 20,
-                  graph: int = 1) -> None:
-    cfg = ks_launch(mode, chunk_bytes, graph, 0)
+                  graph: int = 1, variant: int = 0) -> None:
+    cfg = ks_launch(mode, chunk_bytes, graph, variant)
     _check(lib().ks_launch_set(ctx, max_K, num_series, ctypes.byref(cfg)), "ks_launch_set")
 
 

@@ -5,7 +5,9 @@
 
 Every HIP translation unit is built for gfx950 only, with FMA contraction off
 (so that FP64 decisions made from exact integers round identically everywhere)
-and with packed-FP32 instruction selection disabled.
+and with packed-FP32 instruction selection disabled. libks's sources compile
+to objects in parallel (csrc/ks_scan_variants.hip once per scan-kernel
+variant, -DKS_SCAN_VARIANT=i) and are then linked into the one library.
 """
 
 from __future__ import annotations
@@ -38,6 +40,8 @@ KS_SOURCES = [
     "csrc/ks_stats.hip",
     "csrc/ks_sweep.hip",
 ]
+KS_VARIANT_SOURCE = "csrc/ks_scan_variants.hip"
+KS_SCAN_VARIANTS = 6  # ks_host::kNumVariants
 
 TARGETS = {
     "libks": (PKG / "libks.so", [PKG / s for s in KS_SOURCES], [f"-I{ROOT / 'include'}", f"-I{PKG / 'csrc'}"]),
@@ -52,8 +56,39 @@ def _run(cmd: list[str]) -> None:
         raise RuntimeError(f"build failed: {' '.join(cmd)}")
 
 
+def _jobs() -> int:
+    try:
+        return max(1, min(len(os.sched_getaffinity(0)), int(os.environ.get("MAX_JOBS", "16") or 16)))
+    except (AttributeError, ValueError):
+        return 4
+
+
+def _build_libks(out: Path, extra: list[str]) -> None:
+    """Objects in parallel, then one link (each object carries its own gfx950 code)."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+
+    cflags = [f for f in HIP_FLAGS if f != "-shared"]
+    with tempfile.TemporaryDirectory(prefix="ks_build_") as tmpd:
+        jobs = []
+        for src in KS_SOURCES:
+            jobs.append([HIPCC, *cflags, *extra, "-c", str(PKG / src), "-o", str(Path(tmpd) / (Path(src).stem + ".o"))])
+        for v in range(KS_SCAN_VARIANTS):
+            jobs.append([HIPCC, *cflags, *extra, f"-DKS_SCAN_VARIANT={v}", "-c", str(PKG / KS_VARIANT_SOURCE), "-o",
+                         str(Path(tmpd) / f"ks_scan_variant{v}.o")])
+        with ThreadPoolExecutor(max_workers=_jobs()) as pool:
+            list(pool.map(_run, jobs))
+        objs = [j[-1] for j in jobs]
+        tmp = out.with_suffix(".so.tmp")
+        _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", str(tmp)])
+        os.replace(tmp, out)
+
+
 def build_hip(name: str) -> Path:
     out, srcs, extra = TARGETS[name]
+    if name == "libks":
+        _build_libks(out, extra)
+        return out
     tmp = out.with_suffix(".so.tmp")
     _run([HIPCC, *HIP_FLAGS, *extra, *map(str, srcs), "-o", str(tmp)])
     os.replace(tmp, out)

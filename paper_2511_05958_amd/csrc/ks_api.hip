@@ -28,6 +28,17 @@ int hip_fail(hipError_t e, const char* what) {
   return KS_E_HIP;
 }
 
+// the variant tables, one per object built from ks_scan_variants.hip
+extern const ScanKernels scan_table_0[kNumKClasses], scan_table_1[kNumKClasses], scan_table_2[kNumKClasses],
+    scan_table_3[kNumKClasses], scan_table_4[kNumKClasses], scan_table_5[kNumKClasses];
+static_assert(kNumVariants == 6, "one table per variant");
+
+const ScanKernels& scan_kernels(int kclass, int variant) {
+  static const ScanKernels* const tables[kNumVariants] = {scan_table_0, scan_table_1, scan_table_2,
+                                                          scan_table_3, scan_table_4, scan_table_5};
+  return tables[variant][kclass];
+}
+
 }  // namespace ks_host
 
 // Scratch of ks_scan_batch_noalloc: the ordered plan's header (256 B), then
@@ -125,91 +136,62 @@ struct ScanArgs {
   ks::Workspace ws;
 };
 
-template <int KMAX>
-struct Kernels {
-  static const void* grid() { return reinterpret_cast<const void*>(&ks::scan_kernel<KMAX, kNT, kRB>); }
-  static const void* persistent() { return reinterpret_cast<const void*>(&ks::scan_persistent<KMAX, kNT, kRB>); }
-  static const void* finish() { return reinterpret_cast<const void*>(&ks::finish_kernel<KMAX, kNT, kRB>); }
-};
-
-// kind: 0 grid scan, 1 persistent scan, 2 finish
-const void* kernel_for(int kc, int kind) {
-#define KS_KSEL(KM) \
-  return kind == 0 ? Kernels<KM>::grid() : (kind == 1 ? Kernels<KM>::persistent() : Kernels<KM>::finish())
-  switch (kc) {
-    case 0: KS_KSEL(64);
-    case 1: KS_KSEL(128);
-    case 2: KS_KSEL(256);
-    case 3: KS_KSEL(512);
-    case 4: KS_KSEL(1024);
-    default: KS_KSEL(2048);
-  }
-#undef KS_KSEL
+// Launch the grid scan of variant v (one workgroup per series, descriptor order).
+hipError_t launch_grid(int kc, int v, const ScanArgs& a, hipStream_t st) {
+  ScanArgs x = a;
+  const uint32_t* order = nullptr;
+  void* args[] = {&x.samples, &x.num_samples, &x.desc, &x.num_series, &x.prm, &x.max_K,
+                  &x.out, &x.allU, &x.allU_len, &order};
+  return hipLaunchKernel(scan_kernels(kc, v).grid, dim3(x.num_series), dim3(kVariants[v].nt), args, 0, st);
 }
 
-template <int KMAX>
-hipError_t launch_grid(const ScanArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((ks::scan_kernel<KMAX, kNT, kRB>), dim3(a.num_series), dim3(kNT), 0, st, a.samples,
-                     a.num_samples, a.desc, a.num_series, a.prm, a.max_K, a.out, a.allU, a.allU_len,
-                     (const uint32_t*)nullptr);
-  return hipGetLastError();
-}
-
-hipError_t launch_grid_kc(int kc, const ScanArgs& a, hipStream_t st) {
-  switch (kc) {
-    case 0: return launch_grid<64>(a, st);
-    case 1: return launch_grid<128>(a, st);
-    case 2: return launch_grid<256>(a, st);
-    case 3: return launch_grid<512>(a, st);
-    case 4: return launch_grid<1024>(a, st);
-    default: return launch_grid<2048>(a, st);
-  }
-}
-
-int persistent_grid(ks_ctx* c, int kc, uint32_t& grid) {
-  if (!c->occupancy[kc]) {
+int persistent_grid(ks_ctx* c, int kc, int v, uint32_t& grid) {
+  if (!c->occupancy[kc][v]) {
     int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel_for(kc, 1), kNT, 0);
+    hipError_t e =
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, scan_kernels(kc, v).persistent, kVariants[v].nt, 0);
     if (e != hipSuccess) return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
-    c->occupancy[kc] = nb > 0 ? nb : 1;
+    c->occupancy[kc][v] = nb > 0 ? nb : 1;
   }
-  grid = (uint32_t)(c->num_cus * c->occupancy[kc]);
+  grid = (uint32_t)(c->num_cus * c->occupancy[kc][v]);
   return KS_OK;
 }
 
 // Launch the plan's kernels (directly, or from a cached hipGraph whose kernel
 // arguments are updated for this call).
-int launch_plan(ks_ctx* c, int kc, int mode, const ScanArgs& a, bool use_graph, hipStream_t st) {
-  ScanArgs v = a;
-  const uint32_t* order = reinterpret_cast<const uint32_t*>(v.ws.items);
-  void* plan_args[] = {&v.desc, &v.num_series, &v.num_samples, &v.max_K, &v.chunk, &v.ws};
-  void* grid_args[] = {&v.samples, &v.num_samples, &v.desc, &v.num_series, &v.prm, &v.max_K,
-                       &v.out, &v.allU, &v.allU_len, &order};
-  void* pers_args[] = {&v.samples, &v.num_samples, &v.desc, &v.num_series, &v.prm, &v.max_K,
-                       &v.out, &v.allU, &v.allU_len, &v.chunk, &v.ws};
-  void* fin_args[] = {&v.num_samples, &v.desc, &v.num_series, &v.prm, &v.max_K, &v.out,
-                      &v.allU, &v.allU_len, &v.chunk, &v.ws};
+int launch_plan(ks_ctx* c, int kc, int v, int mode, const ScanArgs& a, bool use_graph, hipStream_t st) {
+  const uint32_t nt = (uint32_t)kVariants[v].nt;
+  const ScanKernels& K = scan_kernels(kc, v);
+  ScanArgs x = a;
+  const uint32_t* order = reinterpret_cast<const uint32_t*>(x.ws.items);
+  void* plan_args[] = {&x.desc, &x.num_series, &x.num_samples, &x.max_K, &x.chunk, &x.ws};
+  void* grid_args[] = {&x.samples, &x.num_samples, &x.desc, &x.num_series, &x.prm, &x.max_K,
+                       &x.out, &x.allU, &x.allU_len, &order};
+  void* pers_args[] = {&x.samples, &x.num_samples, &x.desc, &x.num_series, &x.prm, &x.max_K,
+                       &x.out, &x.allU, &x.allU_len, &x.chunk, &x.ws};
+  void* fin_args[] = {&x.num_samples, &x.desc, &x.num_series, &x.prm, &x.max_K, &x.out,
+                      &x.allU, &x.allU_len, &x.chunk, &x.ws};
   hipKernelNodeParams np[3] = {};
   int n = 0;
   np[n].blockDim = dim3(ks::kPlanNT);
   np[n].gridDim = dim3(1);
   np[n].func = reinterpret_cast<void*>(&ks::plan_kernel);
   np[n++].kernelParams = plan_args;
-  uint32_t grid = v.num_series;
+  uint32_t grid = x.num_series;
   if (mode == KS_LAUNCH_PERSISTENT) {
-    if (int rc = persistent_grid(c, kc, grid)) return rc;
-    np[n].blockDim = dim3(kNT);
+    if (int rc = persistent_grid(c, kc, v, grid)) return rc;
+    np[n].blockDim = dim3(nt);
     np[n].gridDim = dim3(grid);
-    np[n].func = const_cast<void*>(kernel_for(kc, 1));
+    np[n].func = const_cast<void*>(K.persistent);
     np[n++].kernelParams = pers_args;
-    np[n].blockDim = dim3(kNT);
-    np[n].gridDim = dim3(v.num_series);
-    np[n].func = const_cast<void*>(kernel_for(kc, 2));
+    np[n].blockDim = dim3(nt);
+    np[n].gridDim = dim3(x.num_series);
+    np[n].func = const_cast<void*>(K.finish);
     np[n++].kernelParams = fin_args;
   } else {
-    np[n].blockDim = dim3(kNT);
-    np[n].gridDim = dim3(v.num_series);
-    np[n].func = const_cast<void*>(kernel_for(kc, 0));
+    np[n].blockDim = dim3(nt);
+    np[n].gridDim = dim3(x.num_series);
+    np[n].func = const_cast<void*>(K.grid);
     np[n++].kernelParams = grid_args;
   }
   hipError_t e;
@@ -221,8 +203,8 @@ int launch_plan(ks_ctx* c, int kc, int mode, const ScanArgs& a, bool use_graph, 
     return KS_OK;
   }
   // the graph topology depends on the grid sizes only through the nodes'
-  // parameters, so one graph per (mode, K class, persistent grid) is reused
-  auto key = std::make_tuple(mode, kc, mode == KS_LAUNCH_PERSISTENT ? grid : 0u);
+  // parameters, so one graph per (mode, K class, variant, persistent grid) is reused
+  auto key = std::make_tuple(mode, kc, v, mode == KS_LAUNCH_PERSISTENT ? grid : 0u);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     GraphEntry g;
@@ -257,7 +239,7 @@ LaunchCfg config_for(const ks_ctx* c, int kc, uint32_t num_series, uint32_t opts
 
 int scan_with(ks_ctx* ctx, const ScanArgs& a, int kc, const LaunchCfg& cfg, hipStream_t st) {
   if (cfg.mode == KS_LAUNCH_GRID) {
-    hipError_t e = launch_grid_kc(kc, a, st);
+    hipError_t e = launch_grid(kc, cfg.variant, a, st);
     return e == hipSuccess ? KS_OK : hip_fail(e, "scan launch");
   }
   const bool split = cfg.mode == KS_LAUNCH_PERSISTENT;
@@ -265,12 +247,12 @@ int scan_with(ks_ctx* ctx, const ScanArgs& a, int kc, const LaunchCfg& cfg, hipS
   ScanArgs b = a;
   b.chunk = split ? cfg.chunk_bytes : ks::kNoSplit;  // the ordered grid never splits
   b.ws = workspace_of(ctx);
-  return launch_plan(ctx, kc, cfg.mode, b, cfg.graph != 0, st);
+  return launch_plan(ctx, kc, cfg.variant, cfg.mode, b, cfg.graph != 0, st);
 }
 
 bool valid_launch(const ks_launch* c) {
   return c && c->mode <= KS_LAUNCH_ORDERED && c->graph <= 1 && c->chunk_bytes >= 4096u &&
-         c->chunk_bytes <= (1u << 30);
+         c->chunk_bytes <= (1u << 30) && c->variant < (uint32_t)kNumVariants;
 }
 
 LaunchCfg from_launch(const ks_launch* c) {
@@ -278,23 +260,26 @@ LaunchCfg from_launch(const ks_launch* c) {
   l.mode = (int)c->mode;
   l.chunk_bytes = c->chunk_bytes;
   l.graph = (int)c->graph;
+  l.variant = (int)c->variant;
   return l;
 }
 
-ks_launch to_launch(const LaunchCfg& l) { return ks_launch{(uint32_t)l.mode, l.chunk_bytes, (uint32_t)l.graph, 0}; }
+ks_launch to_launch(const LaunchCfg& l) {
+  return ks_launch{(uint32_t)l.mode, l.chunk_bytes, (uint32_t)l.graph, (uint32_t)l.variant};
+}
 
-// Tune-cache lines: "<arch> <cus> <kclass> <num_series> <mode> <chunk_bytes> <graph>".
+// Tune-cache lines: "<arch> <cus> <kclass> <num_series> <mode> <chunk_bytes> <graph> <variant>".
 void load_tune_cache(ks_ctx* c) {
   const char* path = std::getenv("KS_TUNE_CACHE");
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char arch[128];
-  int cus, kc, pers, graph;
+  int cus, kc, pers, graph, var;
   unsigned ns, chunk;
-  while (std::fscanf(f, "%127s %d %d %u %d %u %d", arch, &cus, &kc, &ns, &pers, &chunk, &graph) == 7) {
-    ks_launch l{(uint32_t)pers, chunk, (uint32_t)graph, 0};
-    if (c->arch == arch && cus == c->num_cus && kc >= 0 && kc < kNumKClasses && valid_launch(&l))
+  while (std::fscanf(f, "%127s %d %d %u %d %u %d %d", arch, &cus, &kc, &ns, &pers, &chunk, &graph, &var) == 8) {
+    ks_launch l{(uint32_t)pers, chunk, (uint32_t)graph, (uint32_t)var};
+    if (c->arch == arch && cus == c->num_cus && kc >= 0 && kc < kNumKClasses && var >= 0 && valid_launch(&l))
       c->tuned[std::make_tuple(kc, (uint32_t)ns)] = from_launch(&l);
   }
   std::fclose(f);
@@ -305,7 +290,8 @@ void append_tune_cache(const ks_ctx* c, int kc, uint32_t ns, const LaunchCfg& l)
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %u %d %u %d\n", c->arch.c_str(), c->num_cus, kc, ns, l.mode, l.chunk_bytes, l.graph);
+  std::fprintf(f, "%s %d %d %u %d %u %d %d\n", c->arch.c_str(), c->num_cus, kc, ns, l.mode, l.chunk_bytes, l.graph,
+               l.variant);
   std::fclose(f);
 }
 
@@ -433,15 +419,6 @@ int ks_autotune(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
   const int kc = k_class(max_K);
   hipStream_t st = (hipStream_t)stream;
   ScanArgs a{samples, num_samples, desc, num_series, *params, max_K, out, nullptr, 0, 0, {}};
-  LaunchCfg cands[10];
-  int nc = 0;
-  cands[nc++] = LaunchCfg{KS_LAUNCH_GRID, 1u << 20, 0};
-  cands[nc++] = LaunchCfg{KS_LAUNCH_ORDERED, 1u << 20, 1};
-  cands[nc++] = LaunchCfg{KS_LAUNCH_ORDERED, 1u << 20, 0};
-  for (uint32_t chunk : {1u << 20, 4u << 20, 16u << 20}) {
-    cands[nc++] = LaunchCfg{KS_LAUNCH_PERSISTENT, chunk, 1};
-    cands[nc++] = LaunchCfg{KS_LAUNCH_PERSISTENT, chunk, 0};
-  }
   hipEvent_t e0, e1;
   hipError_t e;
   if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
@@ -449,34 +426,54 @@ int ks_autotune(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
     (void)hipEventDestroy(e0);
     return hip_fail(e, "hipEventCreate");
   }
-  int rc = KS_OK, bi = -1;
-  float bms = 0.f;
-  for (int i = 0; i < nc && rc == KS_OK; ++i) {
-    rc = scan_with(ctx, a, kc, cands[i], st);  // warm-up (builds graphs, grows the workspace)
-    float tmin = 0.f;
+  // one warm-up (builds graphs, grows the workspace), then the best of three
+  auto time_cfg = [&](const LaunchCfg& cfg, float& tmin) -> int {
+    int rc = scan_with(ctx, a, kc, cfg, st);
     for (int r = 0; r < 3 && rc == KS_OK; ++r) {
-      if ((e = hipEventRecord(e0, st)) != hipSuccess) { rc = hip_fail(e, "hipEventRecord"); break; }
-      rc = scan_with(ctx, a, kc, cands[i], st);
-      if (rc) break;
-      if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
-        rc = hip_fail(e, "hipEventSynchronize");
-        break;
-      }
+      if ((e = hipEventRecord(e0, st)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+      if ((rc = scan_with(ctx, a, kc, cfg, st)) != KS_OK) return rc;
+      if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+        return hip_fail(e, "hipEventSynchronize");
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, e0, e1);
       if (r == 0 || ms < tmin) tmin = ms;
     }
-    if (rc == KS_OK && (bi < 0 || tmin < bms)) {
-      bi = i;
-      bms = tmin;
+    return rc;
+  };
+  // every scan-kernel variant (tile, sort radix, walk window) under every
+  // launch plan: the plain grid, the ordered grid from a hipGraph and direct,
+  // the persistent queue with 1 / 4 / 16 MiB splits from a hipGraph and direct
+  // (the variants rank differently under different plans)
+  int rc = KS_OK;
+  LaunchCfg bcfg;
+  float bms = 0.f;
+  bool have = false;
+  for (int v = 0; v < kNumVariants && rc == KS_OK; ++v) {
+    LaunchCfg plans[9];
+    int np = 0;
+    plans[np++] = LaunchCfg{KS_LAUNCH_GRID, 1u << 20, 0, v};
+    plans[np++] = LaunchCfg{KS_LAUNCH_ORDERED, 1u << 20, 1, v};
+    plans[np++] = LaunchCfg{KS_LAUNCH_ORDERED, 1u << 20, 0, v};
+    for (uint32_t chunk : {1u << 20, 4u << 20, 16u << 20}) {
+      plans[np++] = LaunchCfg{KS_LAUNCH_PERSISTENT, chunk, 1, v};
+      plans[np++] = LaunchCfg{KS_LAUNCH_PERSISTENT, chunk, 0, v};
+    }
+    for (int i = 0; i < np && rc == KS_OK; ++i) {
+      float t = 0.f;
+      rc = time_cfg(plans[i], t);
+      if (rc == KS_OK && (!have || t < bms)) {
+        bcfg = plans[i];
+        bms = t;
+        have = true;
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
-  ctx->tuned[std::make_tuple(kc, num_series)] = cands[bi];
-  append_tune_cache(ctx, kc, num_series, cands[bi]);
-  if (best) *best = to_launch(cands[bi]);
+  ctx->tuned[std::make_tuple(kc, num_series)] = bcfg;
+  append_tune_cache(ctx, kc, num_series, bcfg);
+  if (best) *best = to_launch(bcfg);
   if (best_ms) *best_ms = bms;
   return KS_OK;
 }
@@ -501,7 +498,8 @@ int ks_scan_batch_noalloc(ks_ctx* ctx, const uint32_t* samples, uint64_t num_sam
                    reinterpret_cast<uint64_t*>(base + kScratchBase), reinterpret_cast<uint32_t*>(base + kScratchDone),
                    reinterpret_cast<uint32_t*>(base + kScratchMin), nullptr};
   ScanArgs a{samples, num_samples, desc, num_series, *params, max_K, out, all_U, all_U_len, ks::kNoSplit, ws};
-  return launch_plan(ctx, kc, KS_LAUNCH_ORDERED, a, false, (hipStream_t)stream);
+  const int v = config_for(ctx, kc, num_series, 0).variant;  // the tuned kernel variant (a table lookup)
+  return launch_plan(ctx, kc, v, KS_LAUNCH_ORDERED, a, false, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -24,6 +24,30 @@ constexpr int kRB = 4;
 constexpr int kNumKClasses = 6;
 constexpr uint32_t kKClass[kNumKClasses] = {64, 128, 256, 512, 1024, 2048};
 
+// Scan-kernel variants the autotuner chooses among (ks_launch.variant):
+//   nt  workgroup size, i.e. the tile: waves streaming one series' rows and
+//       sorting its keys (and, through the LDS each needs, how many series
+//       stay resident per CU);
+//   rb  bits of the key sort's radix digit (passes = key bits / rb);
+//   gm  the walk window: 64-lane candidate slots a wave walks at once over the
+//       sorted positions (0: its whole share, at most four).
+// Variant 0 is the default. Each is instantiated for every K class and every
+// launch mode (ks_scan_variants.hip, compiled once per variant).
+struct Variant {
+  int nt, rb, gm;
+};
+constexpr int kNumVariants = 6;
+constexpr Variant kVariants[kNumVariants] = {{256, 4, 0}, {128, 4, 0}, {512, 4, 0},
+                                             {256, 8, 0}, {256, 4, 1}, {256, 4, 2}};
+
+// Kernels of one variant and K class: grid / ordered scan, persistent scan, finish.
+struct ScanKernels {
+  const void* grid;
+  const void* persistent;
+  const void* finish;
+};
+const ScanKernels& scan_kernels(int kclass, int variant);
+
 inline int k_class(uint32_t max_K) {
   for (int i = 0; i < kNumKClasses; ++i)
     if (max_K <= kKClass[i]) return i;
@@ -35,6 +59,7 @@ struct LaunchCfg {
   int mode = KS_LAUNCH_ORDERED;  // KS_LAUNCH_GRID / _PERSISTENT / _ORDERED
   uint32_t chunk_bytes = 1u << 20;
   int graph = 1;                 // planned launches replayed from a hipGraph
+  int variant = 0;               // kVariants index
 };
 
 struct GraphEntry {
@@ -123,7 +148,7 @@ struct ks_ctx {
   int device = 0;
   int num_cus = 0;
   std::string arch;
-  int occupancy[ks_host::kNumKClasses] = {0};  // resident workgroups per CU of scan_persistent
+  int occupancy[ks_host::kNumKClasses][ks_host::kNumVariants] = {};  // resident workgroups per CU of scan_persistent
   // scan workspace
   uint32_t* hdr = nullptr;
   ks::Item* items = nullptr;
@@ -132,7 +157,7 @@ struct ks_ctx {
   uint32_t* smin = nullptr;
   ks::RowMom* mom = nullptr;
   uint64_t cap_series = 0, cap_rows = 0;
-  std::map<std::tuple<int, int, uint32_t>, ks_host::GraphEntry> graphs;  // (mode, K class, grid)
+  std::map<std::tuple<int, int, int, uint32_t>, ks_host::GraphEntry> graphs;  // (mode, K class, variant, grid)
   std::map<std::tuple<int, uint32_t>, ks_host::LaunchCfg> tuned;         // (K class, num_series)
   ks_host::LearnBuffers learn;
   ks_host::SegBuffers seg;

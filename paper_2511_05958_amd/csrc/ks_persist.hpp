@@ -78,7 +78,7 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(kPlanNT) void plan_kernel(const ks_desc* __restrict__ desc, uint32_t S,
+static __global__ __launch_bounds__(kPlanNT) void plan_kernel(const ks_desc* __restrict__ desc, uint32_t S,
                                                        uint64_t num_samples, uint32_t max_K, uint32_t chunk_bytes,
                                                        Workspace ws) {
   __shared__ uint32_t hist[kBuckets];
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kPlanNT) void plan_kernel(const ks_desc* __restrict
   }
 }
 
-template <int KMAX, int NT, int RB>
+template <int KMAX, int NT, int RB, int GM = 0>
 __global__ __launch_bounds__(NT) void scan_persistent(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                       const ks_desc* __restrict__ desc, uint32_t num_series,
                                                       ks_params prm, uint32_t max_K, ks_result* __restrict__ out,
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(NT) void scan_persistent(const uint32_t* __restrict
     if (s >= num_series) continue;
     const ks_desc d = desc[s];
     if (item.nchunks <= 1 || check_desc(d, num_samples, max_K)) {
-      scan_one(sm, samples, num_samples, d, prm, max_K, out + s, allU, allU_len);
+      scan_one<KMAX, NT, RB, GM>(sm, samples, num_samples, d, prm, max_K, out + s, allU, allU_len);
       continue;
     }
     // one row range of a split series: moments to the workspace
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(NT) void scan_persistent(const uint32_t* __restrict
 // Completes the series that the plan split (one workgroup per series; the
 // others return at once): gathers their moments and runs keys, sort, walk,
 // choice and p-value.
-template <int KMAX, int NT, int RB>
+template <int KMAX, int NT, int RB, int GM = 0>
 __global__ __launch_bounds__(NT) void finish_kernel(uint64_t num_samples, const ks_desc* __restrict__ desc,
                                                     uint32_t num_series, ks_params prm, uint32_t max_K,
                                                     ks_result* __restrict__ out, uint32_t* __restrict__ allU,
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(NT) void finish_kernel(uint64_t num_samples, const 
   const uint32_t gmin = ws.smin[s];
   __syncthreads();
   const bool fits = allU && d.aux_offset <= allU_len && K <= allU_len - d.aux_offset;
-  finish_series(sm, K, d.N, gmin, prm, out + s, fits ? allU + d.aux_offset : nullptr);
+  finish_series<KMAX, NT, RB, GM>(sm, K, d.N, gmin, prm, out + s, fits ? allU + d.aux_offset : nullptr);
 }
 
 }  // namespace ks

@@ -706,13 +706,15 @@ __device__ __forceinline__ void walk_pass(const uint16_t* __restrict__ is, const
 // with fewer slots than waves, the waves of a slot split the positions (shares
 // of a multiple of 8) and their partial maxima meet in LDS. ties: some two Q
 // are equal. (bU, bC) is the wave's best (bC = 0: none).
-template <int KMAX, int NT, int RB>
+template <int KMAX, int NT, int RB, int GM = 0>
 __device__ void walk_splits(ScanSmem<KMAX, NT, RB>& sm, const uint16_t* __restrict__ is, uint16_t* __restrict__ pos,
                             bool ties, uint32_t K, uint32_t c_lo, uint32_t c_hi, uint32_t* __restrict__ allU,
                             uint32_t& bU, uint32_t& bC) {
   using S = ScanShape<KMAX, NT, RB>;
   constexpr int W = S::W;
-  constexpr int kMaxG = S::CH / W < 1 ? 1 : (S::CH / W > 4 ? 4 : S::CH / W);
+  // slots a wave walks at once: as many as its share (at most 4), or at most GM when GM > 0
+  constexpr int kShareG = S::CH / W < 1 ? 1 : (S::CH / W > 4 ? 4 : S::CH / W);
+  constexpr int kMaxG = GM > 0 && GM < kShareG ? GM : kShareG;
   const uint32_t lane = lane_id(), w = wave_id();
   const uint32_t n = c_hi >= c_lo ? c_hi - c_lo + 1 : 0;
   const uint32_t ns = (n + kWave - 1) / kWave;
@@ -771,7 +773,7 @@ __device__ void walk_splits(ScanSmem<KMAX, NT, RB>& sm, const uint16_t* __restri
 // Phases 4-5 for one series already holding moments in LDS: the walk and the
 // choice cover the candidates c_lo..c_hi (inclusive; 1..K-1 for the full
 // scan); extra_flags are or-ed into the result flags.
-template <int KMAX, int NT, int RB>
+template <int KMAX, int NT, int RB, int GM = 0>
 __device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N, uint32_t gmin,
                               const ks_params& prm, ks_result* __restrict__ out, uint32_t* __restrict__ allU,
                               uint32_t c_lo = 1, uint32_t c_hi = 0xffffffffu, uint32_t extra_flags = 0) {
@@ -804,7 +806,7 @@ __device__ void finish_series(ScanSmem<KMAX, NT, RB>& sm, uint32_t K, uint32_t N
   for (int v = 0; v < S::W; ++v) ties |= sm.red[v] != 0;
 
   uint32_t bU = 0, bC = 0;
-  walk_splits(sm, is, in_pong ? sm.idx : sm.u.pong.idx, ties, K, c_lo, c_hi, allU, bU, bC);
+  walk_splits<KMAX, NT, RB, GM>(sm, is, in_pong ? sm.idx : sm.u.pong.idx, ties, K, c_lo, c_hi, allU, bU, bC);
   if (lane == 0) {
     sm.bestU[w] = bU;
     sm.bestC[w] = bC;
@@ -840,7 +842,7 @@ __device__ __forceinline__ uint32_t check_desc(const ks_desc& d, uint64_t num_sa
   return 0;
 }
 
-template <int KMAX, int NT, int RB>
+template <int KMAX, int NT, int RB, int GM = 0>
 __device__ void scan_one(ScanSmem<KMAX, NT, RB>& sm, const uint32_t* __restrict__ samples, uint64_t num_samples,
                          const ks_desc& d, const ks_params& prm, uint32_t max_K, ks_result* __restrict__ out,
                          uint32_t* __restrict__ allU, uint64_t allU_len) {
@@ -851,13 +853,13 @@ __device__ void scan_one(ScanSmem<KMAX, NT, RB>& sm, const uint32_t* __restrict_
   }
   const uint32_t gmin = stream_moments(sm, samples, d.offset, d.K, d.N);
   const bool fits = allU && d.aux_offset <= allU_len && d.K <= allU_len - d.aux_offset;
-  finish_series(sm, d.K, d.N, gmin, prm, out, fits ? allU + d.aux_offset : nullptr);
+  finish_series<KMAX, NT, RB, GM>(sm, d.K, d.N, gmin, prm, out, fits ? allU + d.aux_offset : nullptr);
 }
 
 // One workgroup per series; with `order`, workgroup b takes series order[b]
 // (the plan's largest-first order, one item per series, 8-byte items whose
 // first word is the series).
-template <int KMAX, int NT, int RB>
+template <int KMAX, int NT, int RB, int GM = 0>
 __global__ __launch_bounds__(NT) void scan_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                   const ks_desc* __restrict__ desc, uint32_t num_series,
                                                   ks_params prm, uint32_t max_K, ks_result* __restrict__ out,
@@ -868,7 +870,7 @@ __global__ __launch_bounds__(NT) void scan_kernel(const uint32_t* __restrict__ s
   const uint32_t s = order ? __builtin_amdgcn_readfirstlane(order[2 * blockIdx.x]) : blockIdx.x;
   if (s >= num_series) return;
   const ks_desc d = desc[s];
-  scan_one(sm, samples, num_samples, d, prm, max_K, out + s, allU, allU_len);
+  scan_one<KMAX, NT, RB, GM>(sm, samples, num_samples, d, prm, max_K, out + s, allU, allU_len);
 }
 
 }  // namespace ks

@@ -31,13 +31,13 @@ LAUNCHES = [(P.KS_LAUNCH_GRID, 1 << 20, 0), (P.KS_LAUNCH_ORDERED, 1 << 20, 1), (
 LAUNCH_IDS = ["grid", "ordered-graph", "ordered-direct", "persistent", "split64k-graph", "split16k-direct"]
 
 
-def run_gpu(ctx, samples, desc, alpha=0.05, max_K=0, allU_len=None, num_samples=None, launch=None):
+def run_gpu(ctx, samples, desc, alpha=0.05, max_K=0, allU_len=None, num_samples=None, launch=None, variant=0):
     import torch
 
     n = len(desc)
     prm = P.ks_params_init(alpha)
     prm.max_K = max_K
-    P.ks_launch_set(ctx.handle, max_K, n, *(launch or DEFAULT_LAUNCH))
+    P.ks_launch_set(ctx.handle, max_K, n, *(launch or DEFAULT_LAUNCH), variant=variant)
     s_d = P.to_device(samples) if len(samples) else torch.zeros(1, dtype=torch.int32, device="cuda")
     d_d = P.to_device(desc) if n else torch.zeros(24, dtype=torch.uint8, device="cuda")
     out = P.empty_results(max(n, 1))
@@ -85,6 +85,47 @@ def test_parity_recipes(ctx, recipe, num, launch):
     assert_parity(g, gU, o, oU, d)
 
 
+VARIANT_LAUNCHES = [(P.KS_LAUNCH_GRID, 1 << 20, 0), (P.KS_LAUNCH_ORDERED, 1 << 20, 1),
+                    (P.KS_LAUNCH_PERSISTENT, 64 << 10, 0)]
+
+
+@pytest.fixture(scope="module")
+def variant_batch():
+    """Recipes 1, 2, 3 and 5 plus a K = 2048 staircase with ties: every K
+    class, long and short walks, several sort passes; with the oracle's
+    results (computed once for all variants)."""
+    rng = np.random.default_rng(17)
+    series = []
+    for recipe, num, first in [(1, 2, 3), (2, 8, 70), (3, 40, 900), (5, 2, 30)]:
+        b = S.make_batch(recipe, num_series=num, first_series=first)
+        x, d = batch_arrays(b)
+        series += [x[int(o):int(o) + int(K) * int(N)].reshape(int(K), int(N)) for o, K, N in
+                   zip(d["offset"], d["K"], d["N"])]
+    series.append(np.repeat((np.arange(2048) // 300 * 11 + 100)[:, None], 5, axis=1).astype(np.uint32)
+                  + rng.integers(0, 3, (2048, 5), dtype=np.uint32))
+    offs, off, xs = [], 0, []
+    for r in series:
+        offs.append(off)
+        xs.append(r.ravel())
+        off += r.size
+    x = np.concatenate(xs)
+    d = P.make_desc(offs, [r.shape[0] for r in series], [r.shape[1] for r in series])
+    o, oU, _ = oracle_batch(x, d)
+    return x, d, o, oU
+
+
+@pytest.mark.parametrize("variant", range(P.KS_SCAN_VARIANTS))
+@pytest.mark.parametrize("launch", VARIANT_LAUNCHES, ids=["grid", "ordered-graph", "split64k-direct"])
+def test_parity_kernel_variants(ctx, variant_batch, variant, launch):
+    """Every scan-kernel variant the autotuner chooses among (tile = workgroup
+    size, radix digit bits of the key sort, walk window) in the grid, ordered
+    and split persistent plans: bit-exact with the oracle."""
+    x, d, o, oU = variant_batch
+    g, gU = run_gpu(ctx, x, d, max_K=2048, launch=launch, variant=variant)
+    assert_parity(g, gU, o, oU, d)
+    assert P.ks_launch_get(ctx.handle, 2048, len(d)).variant == variant
+
+
 def test_graph_replay_with_new_buffers(ctx):
     # same shape (so the cached graph is reused and its arguments updated), different data
     for first in (0, 40, 80):
@@ -105,9 +146,10 @@ def test_autotune_then_scan(ctx):
     prm.max_K = 512
     s_d, d_d, out = P.to_device(x), P.to_device(d), P.empty_results(len(d))
     best, ms = P.ks_autotune(ctx.handle, s_d, d_d, len(d), prm, out)
-    assert best.mode in (0, 1, 2) and ms > 0
+    assert best.mode in (0, 1, 2) and 0 <= best.variant < P.KS_SCAN_VARIANTS and ms > 0
     got = P.ks_launch_get(ctx.handle, 512, len(d))
-    assert (got.mode, got.chunk_bytes, got.graph) == (best.mode, best.chunk_bytes, best.graph)
+    assert (got.mode, got.chunk_bytes, got.graph, got.variant) == (best.mode, best.chunk_bytes, best.graph,
+                                                                    best.variant)
     torch.cuda.synchronize()
     o, oU, _ = oracle_batch(x, d)
     g = P.results_to_numpy(out)
@@ -225,6 +267,9 @@ def test_host_validation(ctx):
     assert e.value.code == P.KS_E_INVALID
     with pytest.raises(ValueError):
         P.ks_scan_batch(ctx.handle, x, d, 2, P.ks_params_init(0.05), out)  # out too small
+    with pytest.raises(P.KsError) as e:
+        P.ks_launch_set(ctx.handle, 64, 1, P.KS_LAUNCH_GRID, 1 << 20, 0, variant=P.KS_SCAN_VARIANTS)
+    assert e.value.code == P.KS_E_RANGE
 
 
 def test_deterministic(ctx):
