@@ -376,8 +376,9 @@ def scan_sources_sha() -> str:
 
 
 def recorded_traffic(kernel: str, workload: str):
-    """HBM bytes per launch measured by rocprofv3 for this kernel and workload on
-    the current sources, or None (no record, or the kernel changed since)."""
+    """HBM bytes per launch measured by rocprofv3 for this kernel configuration
+    (<kernel>:v<variant>:<split bytes>) and workload on the current sources, or
+    None (no record, or the kernel changed since)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
@@ -523,7 +524,8 @@ def plain_scan(args, ctx, key, stream, launch="autotune"):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": recorded_traffic(kernel_name, key),
+            "traffic": recorded_traffic(f"{kernel_name}:v{c.variant}:{c.chunk_bytes if c.mode == P.KS_LAUNCH_PERSISTENT else 0}",
+                                        key),
             "kernel": kernel_name,
             "kernel_ms": avg_kern_s * 1e3,
         },
