@@ -34,7 +34,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 
                                                       uint64_t feat_rows, uint16_t* __restrict__ x0,
                                                       uint32_t SR, LearnWs lw, float* __restrict__ feat_ws) {
   constexpr int W = NT / kWave;
-  constexpr bool kPrefetch = false;  // measured: occupancy hides the row loads better than a prefetch buffer
   __shared__ SelLds sel[W];
   __shared__ uint32_t red[W];
   const uint32_t s = blockIdx.x;
@@ -53,29 +52,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 
   const uint64_t slot = (uint64_t)s * SR + 2;
   SelLds& L = sel[w];
   uint32_t gmin = 0xffffffffu;
-  Batch cur[NB], nxt[NB];
-  if (w < K) load_row<NB>(cur, samples, d.offset + (uint64_t)w * N, N, lane);
+  Batch cur[NB];
+  RowGeo g;
+  if (w < K) g = load_row<NB>(cur, samples, d.offset + (uint64_t)w * N, N, lane);
   for (uint32_t i = w; i < K; i += W) {
-    const uint32_t ni = i + W;
-    if (kPrefetch && ni < K) load_row<NB>(nxt, samples, d.offset + (uint64_t)ni * N, N, lane);
     uint64_t s1, s2;
-    uint32_t s2h, rmax, dec;
-    gmin = min(gmin, row_pass<NB, DecileRanks>(L, cur, N, lane, s1, s2, s2h, rmax, dec));
+    uint32_t s2h;
+    const RowScan rs = row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
+    // the next row's loads are in flight while this row's order statistics are found
+    const RowGeo gi = g;
+    if (i + W < K) g = load_row<NB>(cur, samples, d.offset + (uint64_t)(i + W) * N, N, lane);
     if (lane == 0) {
       lw.s1[slot + i] = s1;
       lw.s2lo[slot + i] = s2;
       lw.s2hi[slot + i] = s2h;
     }
+    const uint32_t dec = row_select<NB, DecileRanks>(L, samples, gi, rs, N, lane);
+    gmin = min(gmin, rs.rmin);
     // feature numerators x - m need the series minimum: keep x itself
     if (lane < 9) feat_ws[(slot + i) * 9 + lane] = __uint_as_float(dec);
-    if (ni < K) {
-      if (kPrefetch) {
-#pragma unroll
-        for (int u = 0; u < NB; ++u) cur[u] = nxt[u];
-      } else {
-        load_row<NB>(cur, samples, d.offset + (uint64_t)ni * N, N, lane);
-      }
-    }
   }
   if (lane == 0) red[w] = gmin;
   __syncthreads();

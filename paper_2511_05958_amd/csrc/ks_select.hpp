@@ -1,8 +1,8 @@
 // Order statistics of rows of uint32 samples, one wave per row: the row held
-// in registers (1, 2 or 4 load batches), its moments (sum r, sum r^2), minimum
-// and maximum by DPP, and a multi-rank MSD radix select for up to nine target
-// ranks. Used by the learned path's decile features and by the per-row
-// latency statistics.
+// in registers (1, 2 or 4 load batches), its minimum and maximum by DPP, its
+// moments (sum r, sum r^2) fused with a histogram of its keys, and a
+// multi-rank select for up to nine target ranks. Used by the learned path's
+// decile features and by the per-row latency statistics.
 #pragma once
 
 #include "ks_scan.hpp"
@@ -23,8 +23,10 @@ namespace ks {
 // and that lane's 16 bins give the bin.
 //
 // Radix levels, for targets that fall into the last bin (and for rows whose
-// keys may equal the empty-slot sentinel): an MSD radix select over the keys
-// of that bin. Level 0 histograms the top kSelW0 bits of every key; each later
+// range needs all 32 bits): an MSD radix select over the keys of that bin.
+// radix_select keeps the keys in registers (key arrays of the workflow
+// checks); stream_select reads a row again from memory at every level, so
+// that the row pass keeps no copy of the row for this rare case. Level 0 histograms the top kSelW0 bits of every key; each later
 // level histograms the next kSelW bits of only the keys that share a target's
 // prefix so far. Those keys form at most nine groups (one per distinct prefix
 // among the targets), numbered in target order. After each level every key is
@@ -166,40 +168,17 @@ __device__ __forceinline__ uint32_t radix_select(SelLds& L, uint32_t (&k)[V], ui
   return key;
 }
 
-// key(e), e < V: this lane's keys (values - row minimum, empty slots
-// kSelEmpty), computed on demand so that no key array stays live through the
-// pass; b >= 1 the bit length of the row's range. Lane j < RANKS::kCount
-// returns the key of rank RANKS::rank(j, N), N the number of keys in the wave.
-// DENSE: only slots e with e % 17 == 16 can be empty (the head / tail slot of
-// each full load batch), so the others skip the check.
-template <int V, class RANKS, bool DENSE, class KeyFn>
-__device__ __forceinline__ uint32_t wave_select_fn(SelLds& L, KeyFn&& keyf, uint32_t b, uint32_t N, uint32_t lane) {
+// Resolves the targets from a window histogram already in L.hist (bins
+// 0 .. kSelWin - 2 count keys of that value, bin kSelWin - 1 every larger key;
+// N keys in all). Lane j < RANKS::kCount gets the bin of the key of rank
+// RANKS::rank(j, N); a target whose bin is the last one gets last = true and
+// r, its rank among the keys of that bin.
+template <class RANKS>
+__device__ __forceinline__ uint32_t window_find(SelLds& L, uint32_t N, uint32_t lane, uint32_t& r, bool& last) {
   static_assert(RANKS::kCount >= 1 && RANKS::kCount <= kSelNone, "at most nine targets");
   const bool tl = lane < RANKS::kCount;
-  const uint32_t R = tl ? RANKS::rank(lane, N) : 0u;
-  if (b >= 32) {  // a key may equal the sentinel: radix levels over every key
-    uint32_t k[V];
-#pragma unroll
-    for (int e = 0; e < V; ++e) k[e] = keyf(e);
-    return radix_select<V>(L, k, b, R, tl, lane);
-  }
-  // window level: bin min(key, kSelWin - 1); empty slots count in a spare word
-  // of their own lane past the window (kSelWin + lane, never read), so that the
-  // row's empty tail slots do not pile onto one address
-  u32x4* hv = reinterpret_cast<u32x4*>(L.hist);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) hv[lane * 4 + i] = u32x4{0u, 0u, 0u, 0u};
   wave_lds_sync();
-#pragma unroll
-  for (int e = 0; e < V; ++e) {
-    const uint32_t x = keyf(e);
-    if (DENSE && e % 17 != 16)
-      atomicAdd(&L.hist[min(x, kSelWin - 1u)], 1u);
-    else
-      atomicAdd(&L.hist[x == kSelEmpty ? kSelWin + lane : min(x, kSelWin - 1u)], 1u);
-    if (V > 17 && e % 17 == 16) __builtin_amdgcn_sched_barrier(0);  // bounds the addresses in flight
-  }
-  wave_lds_sync();
+  const u32x4* hv = reinterpret_cast<const u32x4*>(L.hist);
   // lane l holds bins 16 l .. 16 l + 15: their total, and the wave scan of the totals
   uint32_t t = 0;
 #pragma unroll
@@ -208,18 +187,23 @@ __device__ __forceinline__ uint32_t wave_select_fn(SelLds& L, KeyFn&& keyf, uint
     t += q.x + q.y + q.z + q.w;
   }
   const uint32_t incl = wave_incl_scan(t);
-  // the lane whose bins hold each target's rank: the first whose inclusive count exceeds it
-  uint32_t owner = 0;
+  // per target (its rank is wave-uniform): the first lane whose inclusive
+  // count exceeds it owns the target's bin; lane j keeps target j's rank and owner
+  uint32_t owner = 0, R = 0;
 #pragma unroll
   for (uint32_t j = 0; j < RANKS::kCount; ++j) {
-    const uint32_t Rj = (uint32_t)__builtin_amdgcn_readlane((int)R, (int)j);
+    const uint32_t Rj = RANKS::rank(j, N);
     const uint64_t m = ballot(incl > Rj);  // not empty: Rj < N, the total
     const uint32_t o = m ? (uint32_t)__builtin_ctzll(m) : kWave - 1u;
-    if (lane == j) owner = o;
+    if (lane == j) {
+      owner = o;
+      R = Rj;
+    }
   }
   const uint32_t below = (uint32_t)__shfl((int)(incl - t), (int)owner);  // keys in the owner's lower lanes
-  uint32_t key = 0, r = 0;
-  bool last = false;
+  uint32_t key = 0;
+  r = 0;
+  last = false;
   if (tl) {
     r = R - below;  // rank within the owner's 16 bins
     uint32_t bin = owner * 16u;
@@ -244,6 +228,39 @@ __device__ __forceinline__ uint32_t wave_select_fn(SelLds& L, KeyFn&& keyf, uint
     last = bin == kSelWin - 1u;  // keys >= kSelWin - 1: rank r among them
   }
   wave_lds_sync();
+  return key;
+}
+
+// key(e), e < V: this lane's keys (values - row minimum, empty slots
+// kSelEmpty); b >= 1 the bit length of the range. Lane j < RANKS::kCount
+// returns the key of rank RANKS::rank(j, N), N the number of keys in the wave
+// (wave-uniform).
+template <int V, class RANKS, class KeyFn>
+__device__ __forceinline__ uint32_t wave_select_fn(SelLds& L, KeyFn&& keyf, uint32_t b, uint32_t N, uint32_t lane) {
+  if (b >= 32) {  // a key may equal the sentinel: radix levels over every key
+    const bool tl = lane < RANKS::kCount;
+    const uint32_t R = tl ? RANKS::rank(lane, N) : 0u;
+    uint32_t k[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) k[e] = keyf(e);
+    return radix_select<V>(L, k, b, R, tl, lane);
+  }
+  // window level: bin min(key, kSelWin - 1); empty slots count in a spare word
+  // of their own lane past the window (kSelWin + lane, never read), so that
+  // they do not pile onto one address
+  u32x4* hv = reinterpret_cast<u32x4*>(L.hist);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) hv[lane * 4 + i] = u32x4{0u, 0u, 0u, 0u};
+  wave_lds_sync();
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const uint32_t x = keyf(e);
+    atomicAdd(&L.hist[x == kSelEmpty ? kSelWin + lane : min(x, kSelWin - 1u)], 1u);
+    if (V > 17 && e % 17 == 16) __builtin_amdgcn_sched_barrier(0);  // bounds the addresses in flight
+  }
+  uint32_t r;
+  bool last;
+  const uint32_t key = window_find<RANKS>(L, N, lane, r, last);
   if (ballot(last) == 0) return key;
   // targets in the last bin: radix levels over its keys, relative to its first value
   uint32_t k[V];
@@ -260,13 +277,13 @@ __device__ __forceinline__ uint32_t wave_select_fn(SelLds& L, KeyFn&& keyf, uint
 template <int V, class RANKS>
 __device__ __forceinline__ uint32_t wave_select(SelLds& L, uint32_t (&k)[V], uint32_t b, uint32_t N,
                                                 uint32_t lane) {
-  return wave_select_fn<V, RANKS, false>(L, [&](int e) { return k[e]; }, b, N, lane);
+  return wave_select_fn<V, RANKS>(L, [&](int e) { return k[e]; }, b, N, lane);
 }
 
 // Batches of one row (NB of them; batches past the row's last are empty).
 template <int NB>
-__device__ __forceinline__ void load_row(Batch (&B)[NB], const uint32_t* __restrict__ samples, uint64_t e0,
-                                         uint32_t N, uint32_t lane) {
+__device__ __forceinline__ RowGeo load_row(Batch (&B)[NB], const uint32_t* __restrict__ samples, uint64_t e0,
+                                           uint32_t N, uint32_t lane) {
   const RowGeo g = row_geo(samples, e0, N);
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
@@ -279,6 +296,7 @@ __device__ __forceinline__ void load_row(Batch (&B)[NB], const uint32_t* __restr
       B[u].m = 0;
     }
   }
+  return g;
 }
 
 // Wave totals of a 32-bit and a 64-bit per-lane sum, returned wave-uniform.
@@ -301,72 +319,106 @@ __device__ __forceinline__ void wave_total_32_64(uint32_t& a, uint64_t& c) {
   c = ((uint64_t)hi << 32) | lo;
 }
 
-// Largest row range bit length for which a lane's V keys k < 2^b have
-// sum k^2 < 2^32 (and k < 2^24, the 24-bit multiplier's operand range).
-template <int V>
-__host__ __device__ constexpr uint32_t fast_moment_bits() {
+// Largest row range bit length for which n keys k < 2^b have sum k^2 < 2^32
+// (and k < 2^24, the 24-bit multiplier's operand range).
+__host__ __device__ constexpr uint32_t fast_moment_bits(uint32_t n) {
   uint32_t b = 0;
-  while (b < 24 && (uint64_t)V * (((1ull << (b + 1)) - 1) * ((1ull << (b + 1)) - 1)) < (1ull << 32)) ++b;
+  while (b < 24 && (uint64_t)n * (((1ull << (b + 1)) - 1) * ((1ull << (b + 1)) - 1)) < (1ull << 32)) ++b;
   return b;
 }
+constexpr uint32_t kFastBits = fast_moment_bits(17);  // per load batch (17 samples per lane)
 
-// One row: moments (sum r, sum r^2), minimum, maximum and the order
-// statistics RANKS selects (lanes 0 .. RANKS::kCount - 1).
-// With the row minimum m known first, rows of a small range accumulate the
-// keys k = r - m in 32 bits (sum k, sum k^2 by the 24-bit multiplier) and
-// recover sum r = sum k + N m and sum r^2 = sum k^2 + 2 m sum k + N m^2 once;
-// wider rows take the 96-bit accumulation of the raw samples.
-// FULL: every lane's four quads of every batch hold samples (wave-uniform),
-// so only the head / tail slot needs its validity checked.
-template <int NB, class RANKS, bool FULL>
-__device__ __forceinline__ uint32_t row_pass_impl(SelLds& L, const Batch (&B)[NB], uint32_t N, uint32_t lane,
-                                                  uint64_t& s1, uint64_t& s2, uint32_t& s2h, uint32_t& row_max,
-                                                  uint32_t& dec) {
-  constexpr int V = 17 * NB;
-  auto quad_ok = [&](int u, int q) { return FULL || ((B[u].m >> q) & 1u) != 0u; };
-  uint32_t mn = 0xffffffffu, mx = 0u;
+// Calls quad(v) for every 16-byte quad of the row this lane holds and one(x)
+// for its head / tail sample, then batch_end() after each batch. Batches past
+// the row's last, full batches and batches without a head or tail sample are
+// told apart by wave-uniform tests (g is the row's geometry), so only a
+// partial batch pays a per-lane validity test.
+template <int NB, class Quad, class One, class End>
+__device__ __forceinline__ void for_row(const Batch (&B)[NB], const RowGeo& g, Quad&& quad, One&& one,
+                                        End&& batch_end) {
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
+    if ((uint32_t)u >= g.nb) break;
+    if ((uint32_t)(u + 1) * (4u * kWave) <= g.nq) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (quad_ok(u, q)) {
-        mn = min(mn, min(min(B[u].q[q].x, B[u].q[q].y), min(B[u].q[q].z, B[u].q[q].w)));
-        mx = max(mx, max(max(B[u].q[q].x, B[u].q[q].y), max(B[u].q[q].z, B[u].q[q].w)));
-      }
-    if (B[u].m & 16u) {
-      mn = min(mn, B[u].x);
-      mx = max(mx, B[u].x);
+      for (int q = 0; q < 4; ++q) quad(B[u].q[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((B[u].m >> q) & 1u) quad(B[u].q[q]);
     }
+    if ((uint32_t)u + 1u == g.nb && (g.head | g.tail) != 0u && (B[u].m & 16u)) one(B[u].x);
+    batch_end();
+    __builtin_amdgcn_sched_barrier(0);  // one batch's LDS addresses in flight at a time
   }
-  const uint32_t rmin = wave_min_u32(mn), rmax = wave_max_u32(mx);
-  row_max = rmax;
-  const uint32_t range = rmax - rmin;
-  const uint32_t b = range ? 32u - __clz(range) : 0u;
-  // moments first, from the raw samples, so that the keys can take the
-  // samples' registers afterwards
-  if (b <= fast_moment_bits<V>()) {
-    uint32_t t1 = 0;
-    uint32_t t2 = 0;
-    auto acc = [&](bool v, uint32_t x) {
-      const uint32_t z = v ? x - rmin : 0u;
+}
+
+// Row summary from row_scan, the input of row_select.
+struct RowScan {
+  uint32_t rmin, rmax;
+  uint32_t b;  // bit length of rmax - rmin
+};
+
+// One row (loaded by load_row with geometry g), first part: minimum, maximum,
+// moments (sum r, sum r^2) and the window histogram of the keys r - m (m the
+// row minimum) in L. A first pass takes the minimum and maximum; rows of a
+// range below 2^kFastBits then make one pass that sums k = r - m and k^2 in
+// 32 bits per batch (24-bit multiplier) and counts each key, and recover
+// sum r = sum k + N m, sum r^2 = sum k^2 + 2 m sum k + N m^2 once; wider rows
+// sum the raw samples in 96 bits and count the keys in a second pass. B is
+// not read after this returns, so the caller may load the next row into it
+// while row_select runs.
+template <int NB>
+__device__ __forceinline__ RowScan row_scan(SelLds& L, const Batch (&B)[NB], const RowGeo& g, uint32_t N,
+                                            uint64_t& s1, uint64_t& s2, uint32_t& s2h, uint32_t lane) {
+  // clear the window now: the LDS writes overlap the minimum / maximum pass
+  u32x4* hv = reinterpret_cast<u32x4*>(L.hist);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) hv[lane * 4 + i] = u32x4{0u, 0u, 0u, 0u};
+  uint32_t mn = 0xffffffffu, mx = 0u;
+  for_row(
+      B, g,
+      [&](const u32x4& v) {
+        mn = min(mn, min(min(v.x, v.y), min(v.z, v.w)));
+        mx = max(mx, max(max(v.x, v.y), max(v.z, v.w)));
+      },
+      [&](uint32_t x) {
+        mn = min(mn, x);
+        mx = max(mx, x);
+      },
+      [] {});
+  RowScan rs;
+  rs.rmin = wave_min_u32(mn);
+  rs.rmax = wave_max_u32(mx);
+  const uint32_t rmin = rs.rmin;
+  const uint32_t range = rs.rmax - rmin;
+  rs.b = range ? 32u - __clz(range) : 0u;
+  uint32_t* hist = L.hist;
+  wave_lds_sync();
+  if (rs.b <= kFastBits) {
+    uint32_t t1 = 0, t2b = 0;
+    uint64_t t2 = 0;
+    auto one = [&](uint32_t x) {
+      const uint32_t z = x - rmin;
       t1 += z;
-      t2 += __umul24(z, z);
+      t2b = __umul24(z, z) + t2b;
+      atomicAdd(&hist[min(z, kSelWin - 1u)], 1u);
     };
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bool v = quad_ok(u, q);
-        acc(v, B[u].q[q].x);
-        acc(v, B[u].q[q].y);
-        acc(v, B[u].q[q].z);
-        acc(v, B[u].q[q].w);
-      }
-      acc((B[u].m & 16u) != 0u, B[u].x);
-    }
-    uint64_t t2w = t2;
-    wave_total_32_64(t1, t2w);
-    const u128 q2 = (u128)t2w + (u128)(2ull * rmin) * t1 + (u128)((uint64_t)rmin * rmin) * N;
+    for_row(
+        B, g,
+        [&](const u32x4& v) {
+          one(v.x);
+          one(v.y);
+          one(v.z);
+          one(v.w);
+        },
+        one,
+        [&] {
+          t2 += t2b;
+          t2b = 0;
+        });
+    wave_total_32_64(t1, t2);
+    const u128 q2 = (u128)t2 + (u128)(2ull * rmin) * t1 + (u128)((uint64_t)rmin * rmin) * N;
     s1 = (uint64_t)t1 + (uint64_t)rmin * N;
     s2 = (uint64_t)q2;
     s2h = (uint32_t)(q2 >> 64);
@@ -375,47 +427,136 @@ __device__ __forceinline__ uint32_t row_pass_impl(SelLds& L, const Batch (&B)[NB
     s1 = 0;
     s2 = 0;
     s2h = 0;
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (quad_ok(u, q)) acc_quad(B[u].q[q], unused, s1, s2, s2h);
-      if (B[u].m & 16u) acc_sample(B[u].x, unused, s1, s2, s2h);
-    }
+    for_row(
+        B, g, [&](const u32x4& v) { acc_quad(v, unused, s1, s2, s2h); },
+        [&](uint32_t x) { acc_sample(x, unused, s1, s2, s2h); }, [] {});
     wave_total_64_96(s1, s2, s2h);
+    if (rs.b < 32) {
+      auto one = [&](uint32_t x) { atomicAdd(&hist[min(x - rmin, kSelWin - 1u)], 1u); };
+      for_row(
+          B, g,
+          [&](const u32x4& v) {
+            one(v.x);
+            one(v.y);
+            one(v.z);
+            one(v.w);
+          },
+          one, [] {});
+    }
   }
-  if (b == 0) {
-    dec = rmin;
-    return rmin;
-  }
-  // key of slot e: sample - row minimum (kSelEmpty for a slot without a sample)
-  auto keyf = [&](int e) -> uint32_t {
-    const int u = e / 17, r = e % 17;
-    if (r == 16) return (B[u].m & 16u) ? B[u].x - rmin : kSelEmpty;
-    const int q = r / 4, c = r % 4;
-    const uint32_t x = c == 0 ? B[u].q[q].x : (c == 1 ? B[u].q[q].y : (c == 2 ? B[u].q[q].z : B[u].q[q].w));
-    return quad_ok(u, q) ? x - rmin : kSelEmpty;
-  };
-  dec = wave_select_fn<V, RANKS, FULL>(L, keyf, b, N, lane) + rmin;
-  return rmin;
+  return rs;
 }
 
-// SPECIALISE: rows whose batches are all full take a copy of the pass with the
-// quads' validity checks compiled out. It removes VALU work but costs registers:
-// measured on MI355X it speeds up the statistics kernel (13.2 -> 12.2 ms on
-// 8192 x 1024 x 2048) and slows the feature kernel, whose occupancy it lowers.
-template <int NB, class RANKS, bool SPECIALISE = false>
-__device__ __forceinline__ uint32_t row_pass(SelLds& L, const Batch (&B)[NB], uint32_t N, uint32_t lane,
-                                             uint64_t& s1, uint64_t& s2, uint32_t& s2h, uint32_t& row_max,
-                                             uint32_t& dec) {
-  if constexpr (SPECIALISE) {
-    bool full = true;
+// MSD radix levels over the keys k = r - m - off of the row's samples with
+// r - m >= off (m = rmin), for targets (lanes with tl, at most kSelNone of
+// them, consecutive, ranks R non-decreasing with the lane; R counts among
+// those keys), every key below 2^bits. The row is read again from memory one
+// batch at a time at every level, so that no copy of it stays in registers:
+// this path serves only targets past the window and rows of a range of 2^31
+// or more. The key's group at a level is the index of its prefix among the
+// groups' prefixes (kept in LDS), compared one by one.
+template <int NB>
+__device__ __forceinline__ uint32_t stream_select(SelLds& L, const uint32_t* __restrict__ samples, const RowGeo& g,
+                                               uint32_t rmin, uint32_t off, uint32_t bits, uint32_t R, bool tl,
+                                               uint32_t lane) {
+  uint32_t* gp = reinterpret_cast<uint32_t*>(L.tab);  // prefixes of the groups, in target order
+  const uint64_t tm = ballot(tl);
+  const uint32_t first = tm ? (uint32_t)__builtin_ctzll(tm) : 0u;
+  uint32_t tg = 0, key = 0, G = 1, sprev = bits, wmax = kSelW0;
+  bool level0 = true;  // every key (below 2^bits) is in group 0
+#pragma unroll 1
+  for (;;) {
+    const uint32_t w = min(sprev, wmax);
+    const uint32_t s = sprev - w;
+    const uint32_t nblk = ((G << w) + 255u) >> 8;
+    for (uint32_t i = 0; i < nblk; ++i)
+      *reinterpret_cast<u32x4*>(L.hist + 256u * i + 4u * lane) = u32x4{0u, 0u, 0u, 0u};
+    wave_lds_sync();
+    const uint32_t dmask = (1u << w) - 1u;
+    auto count = [&](uint32_t x) {
+      const uint32_t z = x - rmin;
+      if (z >= off) {
+        const uint32_t k = z - off;
+        uint32_t gid = 0;
+        if (!level0) {
+          const uint32_t h = k >> sprev;
+          gid = kSelNone;
+          for (uint32_t q = 0; q < G; ++q)
+            if (gp[q] == h) gid = q;
+        }
+        if (gid < G) atomicAdd(&L.hist[(gid << w) | ((k >> s) & dmask)], 1u);
+      }
+    };
+#pragma unroll 1
+    for (uint32_t u = 0; u < g.nb; ++u) {
+      Batch t;
+      load_batch(t, samples, g, u, lane);
 #pragma unroll
-    for (int u = 0; u < NB; ++u) full = full && (B[u].m & 15u) == 15u;
-    if (ballot(!full) == 0)
-      return row_pass_impl<NB, RANKS, true>(L, B, N, lane, s1, s2, s2h, row_max, dec);
+      for (int q = 0; q < 4; ++q)
+        if ((t.m >> q) & 1u) {
+          count(t.q[q].x);
+          count(t.q[q].y);
+          count(t.q[q].z);
+          count(t.q[q].w);
+        }
+      if (t.m & 16u) count(t.x);
+    }
+    wave_lds_sync();
+    wave_excl_prefix(L.hist, nblk, lane);
+    wave_lds_sync();
+    uint32_t x = 0;
+    if (tl) {
+      const uint32_t x0 = tg << w;
+      const uint32_t Rg = L.hist[x0] + R;
+      x = x0;
+      for (uint32_t bit = w; bit-- > 0;) {
+        const uint32_t y = x + (1u << bit);
+        if (L.hist[y] <= Rg) x = y;
+      }
+      R = Rg - L.hist[x];
+      key = (key << w) | (x - x0);
+    }
+    if (s == 0) break;
+    // groups of the next level: the targets' distinct bins, in target order
+    const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    const bool fresh = tl && (lane == first || x != prev);
+    const uint64_t m = ballot(fresh);
+    const uint32_t id = mbcnt(m) - (fresh ? 0u : 1u);
+    wave_lds_sync();
+    if (fresh) gp[id] = key;
+    wave_lds_sync();
+    tg = id;
+    G = (uint32_t)__popcll(m);
+    sprev = s;
+    wmax = kSelW;
+    level0 = false;
   }
-  return row_pass_impl<NB, RANKS, false>(L, B, N, lane, s1, s2, s2h, row_max, dec);
+  return key;
+}
+
+// One row, second part (after row_scan): lane j < RANKS::kCount returns the
+// sample of rank RANKS::rank(j, N) in the row.
+template <int NB, class RANKS>
+__device__ __forceinline__ uint32_t row_select(SelLds& L, const uint32_t* __restrict__ samples, const RowGeo& g,
+                                               const RowScan& rs, uint32_t N, uint32_t lane) {
+  if (rs.b == 0) return rs.rmin;
+  uint32_t key = 0, r, off, bits;
+  bool last;
+  if (rs.b >= 32) {  // no window: radix levels over every key
+    last = lane < RANKS::kCount;
+    r = last ? RANKS::rank(lane, N) : 0u;
+    off = 0;
+    bits = 32;
+  } else {
+    key = window_find<RANKS>(L, N, lane, r, last);
+    if (ballot(last) == 0) return key + rs.rmin;
+    // targets in the last bin: radix levels over its keys, relative to its first value
+    off = kSelWin - 1u;
+    const uint32_t top = rs.rmax - rs.rmin - off;
+    bits = top ? 32u - __clz(top) : 1u;
+  }
+  const uint32_t kk = stream_select<NB>(L, samples, g, rs.rmin, off, bits, r, last, lane);
+  return (last ? kk + off : key) + rs.rmin;
 }
 
 // Samples per row handled by the NB-batch feature kernel: a row of N samples

@@ -64,11 +64,17 @@ __global__ __launch_bounds__(256) void row_stats_kernel(const uint32_t* __restri
   const uint32_t K = d.K, N = d.N;
   ks::SelLds& L = sel[w];
   ks::Batch cur[NB];
+  ks::RowGeo g;
+  if (w < K) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)w * N, N, lane);
   for (uint32_t i = w; i < K; i += W) {
-    ks::load_row<NB>(cur, samples, d.offset + (uint64_t)i * N, N, lane);
     uint64_t s1, s2;
-    uint32_t s2h, rmax, sel_x;
-    const uint32_t rmin = ks::row_pass<NB, StatRanks, true>(L, cur, N, lane, s1, s2, s2h, rmax, sel_x);
+    uint32_t s2h;
+    const ks::RowScan rs = ks::row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
+    // the next row's loads are in flight while this row's percentiles are found
+    const ks::RowGeo gi = g;
+    if (i + W < K) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)(i + W) * N, N, lane);
+    const uint32_t sel_x = ks::row_select<NB, StatRanks>(L, samples, gi, rs, N, lane);
+    const uint32_t rmin = rs.rmin, rmax = rs.rmax;
     const uint32_t p95 = (uint32_t)__builtin_amdgcn_readlane((int)sel_x, 1);
     if (lane == 0) {
       const u128 S2 = ((u128)s2h << 64) | s2;

@@ -103,6 +103,17 @@ def _select_stress_series():
         else:  # two clusters far apart: deciles in distinct groups at every level
             r = np.where(rng.random((K, N)) < 0.5, rng.integers(100, 140, (K, N)), rng.integers(3_000_000, 3_000_050, (K, N)))
         out.append(np.asarray(r, np.uint64).astype(np.uint32))
+    # full 32-bit ranges in the two wider classes
+    for N in (2052, 4096):
+        out.append(rng.integers(0, 1 << 32, (3, N), dtype=np.uint64).astype(np.uint32))
+    # upper deciles past the unit-bin window, spread over distinct prefixes
+    for N in (700, 1500, 3000):
+        heavy = rng.integers(2_000, 2_000_000, (4, N))
+        r = np.where(rng.random((4, N)) < 0.55, rng.integers(200, 260, (4, N)), 200 + heavy)
+        out.append(np.asarray(r, np.uint64).astype(np.uint32))
+    # keys at the window's last unit bin and just past it
+    for N in (257, 2049):
+        out.append((300 + rng.choice(np.array([0, 1, 1021, 1022, 1023, 1024, 1025]), (2, N))).astype(np.uint32))
     return out
 
 
