@@ -22,17 +22,16 @@ struct LearnWs {
   uint32_t* K;      // [num_series]: K when the series was valid, 0 otherwise
 };
 
-// Features of one series per workgroup (series whose rows need NB batches;
-// the NB = 1 launch also clears the slots of malformed series). One wave per
-// row, rows w, w + 4, ... for wave w. Writes: the caller's FP32 features
-// (nullable, rows at aux_offset), the network input rows (bf16, 16 channels,
-// 11 used) at row slot s * SR + 2 + i, and the refine workspace.
+// First step, one series per workgroup (series whose rows need NB batches;
+// the NB = 1 launch also marks malformed series with K = 0). One wave per
+// row, rows w, w + 4, ... for wave w. Writes per row the deciles (as raw
+// samples, at row slot s * SR + 2 + i of feat_ws) and the refine workspace's
+// moments, and per series its minimum and K.
 template <int NB, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 : 1))) void features_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                       const ks_desc* __restrict__ desc, uint32_t num_series,
-                                                      uint32_t max_K, float* __restrict__ feat_out,
-                                                      uint64_t feat_rows, uint16_t* __restrict__ x0,
-                                                      uint32_t SR, LearnWs lw, float* __restrict__ feat_ws) {
+                                                      uint32_t max_K, uint32_t SR, LearnWs lw,
+                                                      float* __restrict__ feat_ws) {
   constexpr int W = NT / kWave;
   __shared__ SelLds sel[W];
   __shared__ uint32_t red[W];
@@ -43,8 +42,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 
   const uint32_t w = wave_id();
   const bool bad = check_desc(d, num_samples, max_K) || d.N > KS_FEATURE_MAX_N;
   if ((bad ? 1u : feat_batches(d.N)) != (uint32_t)NB) return;
-  if (bad) {
-    for (uint32_t q = tid; q < SR * 16; q += NT) x0[(uint64_t)s * SR * 16 + q] = 0;
+  if (bad) {  // the pack step zeroes its network input rows
     if (tid == 0) lw.K[s] = 0;
     return;
   }
@@ -74,40 +72,59 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 
   }
   if (lane == 0) red[w] = gmin;
   __syncthreads();
-#pragma unroll
-  for (int u = 0; u < W; ++u) gmin = min(gmin, red[u]);
-  // second sweep: normalise by the series minimum
-  const double denom = (double)(gmin > 1 ? gmin : 1u);
-  const bool to_user = feat_out && d.aux_offset <= feat_rows && K <= feat_rows - d.aux_offset;
-  for (uint32_t q = tid; q < K * 9; q += NT) {
-    const uint32_t i = q / 9, k = q - i * 9;
-    const uint32_t x = __float_as_uint(feat_ws[(slot + i) * 9 + k]);
-    const float f = (float)((double)(x - gmin) / denom);
-    feat_ws[(slot + i) * 9 + k] = f;
-    if (to_user) feat_out[(d.aux_offset + i) * 9 + k] = f;
-  }
-  __syncthreads();
-  // network input: bf16 of the features and the two position channels, 16
-  // channels per row (11..15 zero); the slot's rows outside [2, 2 + K) stay
-  // zero (they are the conv's zero padding)
-  const uint64_t base = (uint64_t)s * SR;
-  for (uint32_t q = tid; q < SR * 16; q += NT) {
-    const uint32_t r = q / 16, k = q - r * 16;
-    uint16_t b = 0;
-    if (r >= 2 && r < K + 2) {
-      if (k < 9)
-        b = cnn::f2bf(feat_ws[(base + r) * 9 + k]);
-      else if (k == 9)
-        b = cnn::f2bf(cnn::pos_frac(r - 2, K));
-      else if (k == 10)
-        b = cnn::f2bf(cnn::pos_centre(r - 2, K));
-    }
-    x0[(base + r) * 16 + k] = b;
-  }
   if (tid == 0) {
+#pragma unroll
+    for (int u = 0; u < W; ++u) gmin = min(gmin, red[u]);
     lw.smin[s] = gmin;
     lw.K[s] = K;
   }
+}
+
+// Second step, one workgroup per series, every slot row r on its own thread:
+// the deciles x of the series' rows become the features
+// f = (double)(x - m) / max(m, 1) rounded to float (m the series minimum), in
+// place and into the caller's buffer, and the network input row (bf16 of the
+// nine features and the two position channels; channels 11..15 zero) is
+// written; slot rows outside [2, 2 + K) (the convolutions' zero padding) and
+// every row of a malformed series (K = 0) are zero.
+template <int NT>
+__global__ __launch_bounds__(NT) void feature_pack_kernel(const ks_desc* __restrict__ desc, uint32_t num_series,
+                                                          float* __restrict__ feat_out, uint64_t feat_rows,
+                                                          uint16_t* __restrict__ x0, uint32_t SR, LearnWs lw,
+                                                          float* __restrict__ feat_ws) {
+  const uint32_t s = blockIdx.x;
+  if (s >= num_series) return;
+  const uint32_t r = blockIdx.y * NT + threadIdx.x;
+  if (r >= SR) return;
+  const uint32_t K = lw.K[s];
+  const uint64_t row = (uint64_t)s * SR + r;
+  u32x4 lo{0u, 0u, 0u, 0u}, hi{0u, 0u, 0u, 0u};
+  if (r >= 2 && r < K + 2) {
+    const uint32_t gmin = lw.smin[s];
+    const double denom = (double)(gmin > 1 ? gmin : 1u);
+    const ks_desc d = desc[s];
+    const bool to_user = feat_out && d.aux_offset <= feat_rows && K <= feat_rows - d.aux_offset;
+    uint16_t b[16];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const uint32_t x = __float_as_uint(feat_ws[row * 9 + k]);
+      const float f = (float)((double)(x - gmin) / denom);
+      feat_ws[row * 9 + k] = f;
+      if (to_user) feat_out[(d.aux_offset + r - 2) * 9 + k] = f;
+      b[k] = cnn::f2bf(f);
+    }
+    b[9] = cnn::f2bf(cnn::pos_frac(r - 2, K));
+    b[10] = cnn::f2bf(cnn::pos_centre(r - 2, K));
+#pragma unroll
+    for (int k = 11; k < 16; ++k) b[k] = 0;
+    lo = u32x4{b[0] | ((uint32_t)b[1] << 16), b[2] | ((uint32_t)b[3] << 16), b[4] | ((uint32_t)b[5] << 16),
+               b[6] | ((uint32_t)b[7] << 16)};
+    hi = u32x4{b[8] | ((uint32_t)b[9] << 16), b[10] | ((uint32_t)b[11] << 16), b[12] | ((uint32_t)b[13] << 16),
+               b[14] | ((uint32_t)b[15] << 16)};
+  }
+  u32x4* dst = reinterpret_cast<u32x4*>(x0 + row * 16);
+  dst[0] = lo;
+  dst[1] = hi;
 }
 
 }  // namespace ks

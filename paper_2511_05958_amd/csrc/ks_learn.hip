@@ -349,11 +349,13 @@ int ks_features(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
   // one launch per row length class (1, 2 or 4 load batches per row); each
   // workgroup whose series belongs to another class returns at once
   hipLaunchKernelGGL((ks::features_kernel<1, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
-                     num_series, max_K, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);
+                     num_series, max_K, SR, learn_ws(ctx), b.feat);
   hipLaunchKernelGGL((ks::features_kernel<2, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
-                     num_series, max_K, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);
+                     num_series, max_K, SR, learn_ws(ctx), b.feat);
   hipLaunchKernelGGL((ks::features_kernel<4, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
-                     num_series, max_K, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);
+                     num_series, max_K, SR, learn_ws(ctx), b.feat);
+  hipLaunchKernelGGL((ks::feature_pack_kernel<kNT>), dim3(num_series, (SR + kNT - 1) / kNT), dim3(kNT), 0, st, desc,
+                     num_series, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "features launch");
   b.stamp_desc = desc;
