@@ -102,7 +102,7 @@ struct SegBuffers {
   uint32_t* wser[2] = {nullptr, nullptr};  // their series
   uint32_t* wstart[2] = {nullptr, nullptr};  // their first row within the series
   ks_result* res = nullptr;                // scan results of the open windows
-  uint32_t* ctr = nullptr;                 // device: next depth's window count, largest K
+  uint32_t* ctr = nullptr;                 // device: per depth d, [2 d] its window count, [2 d + 1] their largest K
   uint32_t* host_ctr = nullptr;            // pinned host copy of ctr
   ks::RowMom* rows = nullptr;              // per-row moments and minimum of depth 0 (s * max_K + i)
   uint64_t cap = 0;                        // windows per buffer

@@ -6,6 +6,9 @@
 // read that workspace and never the samples. After each depth a split kernel
 // records the significant splits and opens both sides of each as windows of
 // the next depth; a final kernel sorts each series' boundaries by position.
+// Window and split kernels run on fixed grids that stride over the depth's
+// window count in device memory, so the host enqueues several depths between
+// read-backs of those counts.
 #include <hip/hip_runtime.h>
 
 #include <new>
@@ -31,6 +34,9 @@ void free_seg(SegBuffers& b) {
 namespace {
 
 constexpr uint32_t kSegNT = 256;
+constexpr uint32_t kSegGrid = 2048;      // workgroups of a window-scan launch (grid-stride over the windows)
+constexpr uint32_t kSegSplitGrid = 256;  // workgroups of a split launch
+constexpr uint32_t kSegDepths = KS_MAX_K + 1;  // counter pairs: a window of a later depth is a part of one before it
 
 // Depth 0: the full scan of series blockIdx.x (as scan_kernel), also storing
 // each row's moments and minimum at rows[s * row_stride + i].
@@ -64,34 +70,38 @@ __global__ __launch_bounds__(kNT) void seg_root_kernel(const uint32_t* __restric
   ks::finish_series(sm, d.K, d.N, gmin, prm, out + s, nullptr);
 }
 
-// Depth >= 1: window t (series wser[t], rows wstart[t] .. + win[t].K) from the
-// stored row moments; its eq. 2 minimum is the least of its rows' minima.
+// Depth >= 1: windows t = blockIdx.x, + gridDim.x, ... below *count (series
+// wser[t], rows wstart[t] .. + win[t].K) from the stored row moments; a
+// window's eq. 2 minimum is the least of its rows' minima.
 template <int KMAX>
-__global__ __launch_bounds__(kNT) void seg_window_kernel(const ks_desc* __restrict__ win, uint32_t n,
+__global__ __launch_bounds__(kNT) void seg_window_kernel(const ks_desc* __restrict__ win,
+                                                         const uint32_t* __restrict__ count,
                                                          const uint32_t* __restrict__ wser,
                                                          const uint32_t* __restrict__ wstart, ks_params prm,
                                                          const ks::RowMom* __restrict__ rows, uint32_t row_stride,
                                                          ks_result* __restrict__ out) {
   __shared__ ks::ScanSmem<KMAX, kNT, kRB> sm;
-  const uint32_t t = blockIdx.x;
-  if (t >= n) return;
-  const ks_desc d = win[t];
-  const uint32_t K = d.K;
-  if (K < 2 || K > (uint32_t)KMAX) {  // never opened by the split kernel
-    if (threadIdx.x == 0) ks::write_result(out + t, 0, 0, 0, 0, 0.0, 0.0, 1.0, KS_BAD_SHAPE);
-    return;
+  const uint32_t n = *count;
+  for (uint32_t t = blockIdx.x; t < n; t += gridDim.x) {
+    __syncthreads();  // the previous window's reads of sm are done
+    const ks_desc d = win[t];
+    const uint32_t K = d.K;
+    if (K < 2 || K > (uint32_t)KMAX) {  // never opened by the split kernel
+      if (threadIdx.x == 0) ks::write_result(out + t, 0, 0, 0, 0, 0.0, 0.0, 1.0, KS_BAD_SHAPE);
+      continue;
+    }
+    const ks::RowMom* rm = rows + (uint64_t)wser[t] * row_stride + wstart[t];
+    uint32_t mn = 0xffffffffu;
+    for (uint32_t i = threadIdx.x; i < K; i += kNT) {
+      const ks::RowMom r = rm[i];
+      sm.u.mom.s1[i] = r.s1;
+      sm.u.mom.s2lo[i] = r.s2lo;
+      sm.u.mom.s2hi[i] = r.s2hi;
+      mn = min(mn, r.pad);
+    }
+    const uint32_t gmin = ks::block_min_u32<kNT>(mn, sm.red);  // its barriers also publish the moments
+    ks::finish_series(sm, K, d.N, gmin, prm, out + t, nullptr);
   }
-  const ks::RowMom* rm = rows + (uint64_t)wser[t] * row_stride + wstart[t];
-  uint32_t mn = 0xffffffffu;
-  for (uint32_t i = threadIdx.x; i < K; i += kNT) {
-    const ks::RowMom r = rm[i];
-    sm.u.mom.s1[i] = r.s1;
-    sm.u.mom.s2lo[i] = r.s2lo;
-    sm.u.mom.s2hi[i] = r.s2hi;
-    mn = min(mn, r.pad);
-  }
-  const uint32_t gmin = ks::block_min_u32<kNT>(mn, sm.red);  // its barriers also publish the moments
-  ks::finish_series(sm, K, d.N, gmin, prm, out + t, nullptr);
 }
 
 template <template <int> class KERNEL, typename... Args>
@@ -114,24 +124,26 @@ struct WindowK {
   static constexpr auto f = seg_window_kernel<KMAX>;
 };
 
-// One thread per open window of depth `depth`. Window t is series wser[t]
-// (t itself at depth 0) starting at row wstart[t] (0 at depth 0).
+// One thread per open window of depth `depth` (n of them, or *count when
+// count is given), grid-stride. Window t is series wser[t] (t itself at
+// depth 0) starting at row wstart[t] (0 at depth 0). ctr: the next depth's
+// window count and largest K.
 __global__ __launch_bounds__(kSegNT) void seg_split_kernel(
-    const ks_desc* __restrict__ win, const ks_result* __restrict__ res, uint32_t n,
+    const ks_desc* __restrict__ win, const ks_result* __restrict__ res, uint32_t n, const uint32_t* __restrict__ count,
     const uint32_t* __restrict__ wser, const uint32_t* __restrict__ wstart, uint32_t depth, int open_next,
     ks_desc* __restrict__ next, uint32_t* __restrict__ nser, uint32_t* __restrict__ nstart, uint32_t* __restrict__ ctr,
     uint64_t cap, ks_result* __restrict__ cps, uint32_t* __restrict__ counts, uint32_t max_cp) {
-  const uint32_t t = blockIdx.x * kSegNT + threadIdx.x;
-  if (t >= n) return;
+  if (count) n = *count;
+  for (uint32_t t = blockIdx.x * kSegNT + threadIdx.x; t < n; t += gridDim.x * kSegNT) {
   const ks_result r = res[t];
   const uint32_t s = wser ? wser[t] : t;
   const uint32_t a = wstart ? wstart[t] : 0u;
   if (r.flags & (KS_BAD_SHAPE | KS_OUT_OF_RANGE)) {
     // only a caller's descriptor can be malformed: every later window lies inside a valid series
     if (depth == 0) counts[s] = KS_SEGMENT_BAD;
-    return;
+    continue;
   }
-  if (!(r.flags & KS_SIGNIFICANT)) return;
+  if (!(r.flags & KS_SIGNIFICANT)) continue;
   const ks_desc d = win[t];
   const uint32_t slot = atomicAdd(&counts[s], 1u);
   if (slot < max_cp) {
@@ -140,7 +152,7 @@ __global__ __launch_bounds__(kSegNT) void seg_split_kernel(
     o.pad = depth;
     cps[(uint64_t)s * max_cp + slot] = o;
   }
-  if (!open_next) return;
+  if (!open_next) continue;
   const uint32_t kl = r.cp, kr = d.K - r.cp;
   if (kl >= 2) {
     const uint32_t i = atomicAdd(&ctr[0], 1u);
@@ -159,6 +171,7 @@ __global__ __launch_bounds__(kSegNT) void seg_split_kernel(
       nstart[i] = a + r.cp;
       atomicMax(&ctr[1], kr);
     }
+  }
   }
 }
 
@@ -198,10 +211,10 @@ int ensure_seg(ks_ctx* c, uint64_t cap, uint64_t rows) {
   if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
   free_seg(b);
   bool ok = alloc(b.win[0], cap) && alloc(b.win[1], cap) && alloc(b.wser[0], cap) && alloc(b.wser[1], cap) &&
-            alloc(b.wstart[0], cap) && alloc(b.wstart[1], cap) && alloc(b.res, cap) && alloc(b.ctr, 2) &&
-            alloc(b.rows, rows) &&
-            hipHostMalloc(reinterpret_cast<void**>(&b.host_ctr), 2 * sizeof(uint32_t), hipHostMallocDefault) ==
-                hipSuccess;
+            alloc(b.wstart[0], cap) && alloc(b.wstart[1], cap) && alloc(b.res, cap) &&
+            alloc(b.ctr, 2 * kSegDepths) && alloc(b.rows, rows) &&
+            hipHostMalloc(reinterpret_cast<void**>(&b.host_ctr), 2 * kSegDepths * sizeof(uint32_t),
+                          hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     free_seg(b);
     (void)hipGetLastError();
@@ -232,37 +245,51 @@ extern "C" int ks_segment_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t n
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * num_series, st);
   if (e != hipSuccess) return hip_fail(e, "counts reset");
-  const ks_desc* cur = desc;
-  const uint32_t* cser = nullptr;
-  const uint32_t* cstart = nullptr;
-  uint64_t n = num_series;
+  if ((e = hipMemsetAsync(b.ctr, 0, 2 * sizeof(uint32_t) * kSegDepths, st)) != hipSuccess)
+    return hip_fail(e, "window counters");
+  // a window of depth d >= 1 has at most max_K - d rows, so depth max_K - 1 opens none
+  const uint32_t limit = max_levels == 0 || max_levels > max_K - 1 ? max_K - 1 : max_levels;
+  const uint32_t wgrid = (uint32_t)(b.cap < kSegGrid ? b.cap : kSegGrid);
+  const uint32_t sgrid = (uint32_t)((b.cap + kSegNT - 1) / kSegNT < kSegSplitGrid ? (b.cap + kSegNT - 1) / kSegNT
+                                                                                     : kSegSplitGrid);
+  // depth 0: every series
+  launch_kc<RootK>(k_class(max_K), num_series, st, samples, num_samples, desc, num_series, *params, max_K, b.res,
+                   b.rows, max_K);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "root scan launch");
+  hipLaunchKernelGGL(seg_split_kernel, dim3((num_series + kSegNT - 1) / kSegNT), dim3(kSegNT), 0, st, desc, b.res,
+                     num_series, (const uint32_t*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0u,
+                     (int)(limit > 1), b.win[0], b.wser[0], b.wstart[0], b.ctr + 2, b.cap, cps, counts, max_cp);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "split launch");
+  // later depths in chunks of 4, 8, 16, ... between read-backs of their window counts; a
+  // depth whose count is 0 costs two near-empty launches
   uint32_t roundK = max_K;
-  int dst = 0;
-  for (uint32_t depth = 0; n > 0 && (max_levels == 0 || depth < max_levels); ++depth) {
-    if (depth == 0)
-      launch_kc<RootK>(k_class(max_K), (uint32_t)n, st, samples, num_samples, desc, num_series, *params, max_K, b.res,
-                       b.rows, max_K);
-    else
-      launch_kc<WindowK>(k_class(roundK), (uint32_t)n, st, cur, (uint32_t)n, cser, cstart, *params,
-                         (const ks::RowMom*)b.rows, max_K, b.res);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "window scan launch");
-    const int open_next = max_levels == 0 || depth + 1 < max_levels;
-    if ((e = hipMemsetAsync(b.ctr, 0, 2 * sizeof(uint32_t), st)) != hipSuccess) return hip_fail(e, "window counter");
-    hipLaunchKernelGGL(seg_split_kernel, dim3((uint32_t)((n + kSegNT - 1) / kSegNT)), dim3(kSegNT), 0, st, cur, b.res,
-                       (uint32_t)n, cser, cstart, depth, open_next, b.win[dst], b.wser[dst], b.wstart[dst], b.ctr, b.cap,
-                       cps, counts, max_cp);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "split launch");
-    if (!open_next) break;
-    if ((e = hipMemcpyAsync(b.host_ctr, b.ctr, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+  uint32_t depth = 1, chunk = 4;
+  while (depth < limit) {
+    const uint32_t end = depth + chunk < limit ? depth + chunk : limit;
+    for (uint32_t d = depth; d < end; ++d) {
+      const int src = (d - 1) & 1, dst = d & 1;
+      launch_kc<WindowK>(k_class(roundK), wgrid, st, b.win[src], (const uint32_t*)(b.ctr + 2 * d), b.wser[src],
+                         b.wstart[src], *params, (const ks::RowMom*)b.rows, max_K, b.res);
+      if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "window scan launch");
+      hipLaunchKernelGGL(seg_split_kernel, dim3(sgrid), dim3(kSegNT), 0, st, b.win[src], b.res, 0u,
+                         (const uint32_t*)(b.ctr + 2 * d), b.wser[src], b.wstart[src], d, (int)(d + 1 < limit),
+                         b.win[dst], b.wser[dst], b.wstart[dst], b.ctr + 2 * (d + 1), b.cap, cps, counts, max_cp);
+      if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "split launch");
+    }
+    // counts of depths depth + 1 .. end
+    if ((e = hipMemcpyAsync(b.host_ctr, b.ctr + 2 * (depth + 1), 2 * sizeof(uint32_t) * (end - depth),
+                            hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "window count");
-    if (b.host_ctr[0] > b.cap) return KS_E_STATE;  // cannot happen: windows of a depth are disjoint
-    n = b.host_ctr[0];
-    roundK = b.host_ctr[1] >= 2 ? b.host_ctr[1] : 2;
-    cur = b.win[dst];
-    cser = b.wser[dst];
-    cstart = b.wstart[dst];
-    dst ^= 1;
+    bool open = false;
+    for (uint32_t d = 0; d < end - depth; ++d) {
+      if (b.host_ctr[2 * d] > b.cap) return KS_E_STATE;  // cannot happen: windows of a depth are disjoint
+      open = b.host_ctr[2 * d] > 0;
+      if (open && b.host_ctr[2 * d + 1] >= 2) roundK = b.host_ctr[2 * d + 1];
+    }
+    if (!open) break;
+    depth = end;
+    chunk *= 2;
   }
   hipLaunchKernelGGL(seg_sort_kernel, dim3((num_series + kSegNT - 1) / kSegNT), dim3(kSegNT), 0, st, cps, counts,
                      num_series, max_cp);
