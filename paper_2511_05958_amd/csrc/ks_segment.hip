@@ -38,15 +38,18 @@ constexpr uint32_t kSegGrid = 2048;      // workgroups of a window-scan launch (
 constexpr uint32_t kSegSplitGrid = 256;  // workgroups of a split launch
 constexpr uint32_t kSegDepths = KS_MAX_K + 1;  // counter pairs: a window of a later depth is a part of one before it
 
-// Depth 0: the full scan of series blockIdx.x (as scan_kernel), also storing
-// each row's moments and minimum at rows[s * row_stride + i].
+// Depth 0: the full scan of series blockIdx.x (as scan_kernel, in workgroups
+// of kSegRootNT threads: the streaming depth is HBM-bound like the plain
+// scan), also storing each row's moments and minimum at rows[s * row_stride + i].
+constexpr int kSegRootNT = 512;
+
 template <int KMAX>
-__global__ __launch_bounds__(kNT) void seg_root_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
+__global__ __launch_bounds__(kSegRootNT) void seg_root_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                        const ks_desc* __restrict__ desc, uint32_t num_series,
                                                        ks_params prm, uint32_t max_K, ks_result* __restrict__ out,
                                                        ks::RowMom* __restrict__ rows, uint32_t row_stride) {
-  using S = ks::ScanShape<KMAX, kNT, kRB>;
-  __shared__ ks::ScanSmem<KMAX, kNT, kRB> sm;
+  using S = ks::ScanShape<KMAX, kSegRootNT, kRB>;
+  __shared__ ks::ScanSmem<KMAX, kSegRootNT, kRB> sm;
   const uint32_t s = blockIdx.x;
   if (s >= num_series) return;
   const ks_desc d = desc[s];
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(kNT) void seg_root_kernel(const uint32_t* __restric
                                                 rm[i] = ks::RowMom{s1, s2, s2h, rmin};
                                               }
                                             });
-  const uint32_t gmin = ks::block_min_u32<kNT>(mn, sm.red);
+  const uint32_t gmin = ks::block_min_u32<kSegRootNT>(mn, sm.red);
   ks::finish_series(sm, d.K, d.N, gmin, prm, out + s, nullptr);
 }
 
@@ -107,21 +110,23 @@ __global__ __launch_bounds__(kNT) void seg_window_kernel(const ks_desc* __restri
 template <template <int> class KERNEL, typename... Args>
 void launch_kc(int kc, uint32_t grid, hipStream_t st, Args... args) {
   switch (kc) {
-    case 0: hipLaunchKernelGGL(KERNEL<64>::f, dim3(grid), dim3(kNT), 0, st, args...); break;
-    case 1: hipLaunchKernelGGL(KERNEL<128>::f, dim3(grid), dim3(kNT), 0, st, args...); break;
-    case 2: hipLaunchKernelGGL(KERNEL<256>::f, dim3(grid), dim3(kNT), 0, st, args...); break;
-    case 3: hipLaunchKernelGGL(KERNEL<512>::f, dim3(grid), dim3(kNT), 0, st, args...); break;
-    case 4: hipLaunchKernelGGL(KERNEL<1024>::f, dim3(grid), dim3(kNT), 0, st, args...); break;
-    default: hipLaunchKernelGGL(KERNEL<2048>::f, dim3(grid), dim3(kNT), 0, st, args...);
+    case 0: hipLaunchKernelGGL(KERNEL<64>::f, dim3(grid), dim3(KERNEL<64>::nt), 0, st, args...); break;
+    case 1: hipLaunchKernelGGL(KERNEL<128>::f, dim3(grid), dim3(KERNEL<128>::nt), 0, st, args...); break;
+    case 2: hipLaunchKernelGGL(KERNEL<256>::f, dim3(grid), dim3(KERNEL<256>::nt), 0, st, args...); break;
+    case 3: hipLaunchKernelGGL(KERNEL<512>::f, dim3(grid), dim3(KERNEL<512>::nt), 0, st, args...); break;
+    case 4: hipLaunchKernelGGL(KERNEL<1024>::f, dim3(grid), dim3(KERNEL<1024>::nt), 0, st, args...); break;
+    default: hipLaunchKernelGGL(KERNEL<2048>::f, dim3(grid), dim3(KERNEL<2048>::nt), 0, st, args...);
   }
 }
 template <int KMAX>
 struct RootK {
   static constexpr auto f = seg_root_kernel<KMAX>;
+  static constexpr int nt = kSegRootNT;
 };
 template <int KMAX>
 struct WindowK {
   static constexpr auto f = seg_window_kernel<KMAX>;
+  static constexpr int nt = kNT;
 };
 
 // One thread per open window of depth `depth` (n of them, or *count when
