@@ -261,7 +261,10 @@ int ks_scan_batch_noalloc(ks_ctx *ctx, const uint32_t *samples, uint64_t num_sam
  * ------------------------------------------------------------------------ */
 
 #define KS_CNN_PARAMS 44993u
-#define KS_FEATURE_MAX_N 4096u /* largest N the feature pass accepts */
+/* Largest N the feature and statistics passes accept: every row length the
+ * scan accepts. Rows of up to 4096 + 3 samples are held in registers; longer
+ * rows are streamed through the same order-statistics select. */
+#define KS_FEATURE_MAX_N KS_MAX_N
 
 typedef struct ks_model ks_model;
 

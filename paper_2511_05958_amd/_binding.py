@@ -19,7 +19,7 @@ KS_VERSION = 10000
 KS_MAX_K = 2048
 KS_MAX_N = 1 << 24
 KS_CNN_PARAMS = 44993
-KS_FEATURE_MAX_N = 4096
+KS_FEATURE_MAX_N = 1 << 24  # = KS_MAX_N
 KS_NOALLOC_MAX_SERIES = 1 << 19
 KS_CNN_TRACE_ACTS = 204
 KS_CNN_TRACE_GRADS = 193

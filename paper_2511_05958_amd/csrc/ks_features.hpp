@@ -22,11 +22,12 @@ struct LearnWs {
   uint32_t* K;      // [num_series]: K when the series was valid, 0 otherwise
 };
 
-// First step, one series per workgroup (series whose rows need NB batches;
-// the NB = 1 launch also marks malformed series with K = 0). One wave per
-// row, rows w, w + 4, ... for wave w. Writes per row the deciles (as raw
-// samples, at row slot s * SR + 2 + i of feat_ws) and the refine workspace's
-// moments, and per series its minimum and K.
+// First step, one series per workgroup (series of row class NB: rows in 1,
+// 2 or 4 load batches held in registers, or kStreamed; the NB = 1 launch also
+// marks malformed series with K = 0). One wave per row, rows w, w + 4, ...
+// for wave w. Writes per row the deciles (as raw samples, at row slot
+// s * SR + 2 + i of feat_ws) and the refine workspace's moments, and per
+// series its minimum and K.
 template <int NB, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 : 1))) void features_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                       const ks_desc* __restrict__ desc, uint32_t num_series,
@@ -50,25 +51,32 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 
   const uint64_t slot = (uint64_t)s * SR + 2;
   SelLds& L = sel[w];
   uint32_t gmin = 0xffffffffu;
-  Batch cur[NB];
-  RowGeo g;
-  if (w < K) g = load_row<NB>(cur, samples, d.offset + (uint64_t)w * N, N, lane);
-  for (uint32_t i = w; i < K; i += W) {
-    uint64_t s1, s2;
-    uint32_t s2h;
-    const RowScan rs = row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
-    // the next row's loads are in flight while this row's order statistics are found
-    const RowGeo gi = g;
-    if (i + W < K) g = load_row<NB>(cur, samples, d.offset + (uint64_t)(i + W) * N, N, lane);
+  auto emit = [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t rmin, uint32_t dec) {
     if (lane == 0) {
       lw.s1[slot + i] = s1;
       lw.s2lo[slot + i] = s2;
       lw.s2hi[slot + i] = s2h;
     }
-    const uint32_t dec = row_select<NB, DecileRanks>(L, samples, gi, rs, N, lane);
-    gmin = min(gmin, rs.rmin);
+    gmin = min(gmin, rmin);
     // feature numerators x - m need the series minimum: keep x itself
     if (lane < 9) feat_ws[(slot + i) * 9 + lane] = __uint_as_float(dec);
+  };
+  if constexpr (NB == (int)kStreamed) {
+    select_rows_long<DecileRanks>(L, samples, d.offset, N, K, w, W, lane,
+                                  [&](uint32_t i, const RowOut& o) { emit(i, o.s1, o.s2, o.s2h, o.rmin, o.sel); });
+  } else {
+    Batch cur[NB];
+    RowGeo g;
+    if (w < K) g = load_row<NB>(cur, samples, d.offset + (uint64_t)w * N, N, lane);
+    for (uint32_t i = w; i < K; i += W) {
+      uint64_t s1, s2;
+      uint32_t s2h;
+      const RowScan rs = row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
+      // the next row's loads are in flight while this row's order statistics are found
+      const RowGeo gi = g;
+      if (i + W < K) g = load_row<NB>(cur, samples, d.offset + (uint64_t)(i + W) * N, N, lane);
+      emit(i, s1, s2, s2h, rs.rmin, row_select<NB, DecileRanks>(L, samples, gi, rs, N, lane));
+    }
   }
   if (lane == 0) red[w] = gmin;
   __syncthreads();

@@ -346,7 +346,7 @@ int ks_features(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
   if (int rc = ensure_learn(ctx, (uint64_t)num_series * SR, num_series, false)) return rc;
   hipStream_t st = (hipStream_t)stream;
   LearnBuffers& b = ctx->learn;
-  // one launch per row length class (1, 2 or 4 load batches per row); each
+  // one launch per row class (1, 2 or 4 load batches per row, or streamed); each
   // workgroup whose series belongs to another class returns at once
   hipLaunchKernelGGL((ks::features_kernel<1, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
                      num_series, max_K, SR, learn_ws(ctx), b.feat);
@@ -354,6 +354,8 @@ int ks_features(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
                      num_series, max_K, SR, learn_ws(ctx), b.feat);
   hipLaunchKernelGGL((ks::features_kernel<4, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
                      num_series, max_K, SR, learn_ws(ctx), b.feat);
+  hipLaunchKernelGGL((ks::features_kernel<ks::kStreamed, kNT>), dim3(num_series), dim3(kNT), 0, st, samples,
+                     num_samples, desc, num_series, max_K, SR, learn_ws(ctx), b.feat);
   hipLaunchKernelGGL((ks::feature_pack_kernel<kNT>), dim3(num_series, (SR + kNT - 1) / kNT), dim3(kNT), 0, st, desc,
                      num_series, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);
   hipError_t e = hipGetLastError();

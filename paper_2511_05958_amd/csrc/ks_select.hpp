@@ -84,6 +84,21 @@ __device__ __forceinline__ void wave_excl_prefix(uint32_t* hist, uint32_t nblk, 
   }
 }
 
+// The same with full 32-bit counts (rows of 2^16 samples or more), one
+// 256-bin block per wave scan.
+__device__ __forceinline__ void wave_excl_prefix32(uint32_t* hist, uint32_t nblk, uint32_t lane) {
+  uint32_t base = 0;
+  for (uint32_t i = 0; i < nblk; ++i) {
+    u32x4* pa = reinterpret_cast<u32x4*>(hist + 256u * i + 4u * lane);
+    const u32x4 a = *pa;
+    const uint32_t sa = a.x + a.y + a.z + a.w;
+    const uint32_t incl = wave_incl_scan(sa);
+    const uint32_t ea = base + incl - sa;
+    *pa = u32x4{ea, ea + a.x, ea + a.x + a.y, ea + a.x + a.y + a.z};
+    base += (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+  }
+}
+
 // Target ranks of a select: RANKS::kCount <= 9 targets, RANKS::rank(j, N)
 // non-decreasing in j.
 // The nine deciles x_(floor(k (N - 1) / 10)), k = 1..9.
@@ -454,8 +469,8 @@ __device__ __forceinline__ RowScan row_scan(SelLds& L, const Batch (&B)[NB], con
 // batch at a time at every level, so that no copy of it stays in registers:
 // this path serves only targets past the window and rows of a range of 2^31
 // or more. The key's group at a level is the index of its prefix among the
-// groups' prefixes (kept in LDS), compared one by one.
-template <int NB>
+// groups' prefixes (kept in LDS), compared one by one. Counts are full 32-bit
+// (rows of any length).
 __device__ __forceinline__ uint32_t stream_select(SelLds& L, const uint32_t* __restrict__ samples, const RowGeo& g,
                                                uint32_t rmin, uint32_t off, uint32_t bits, uint32_t R, bool tl,
                                                uint32_t lane) {
@@ -502,7 +517,7 @@ __device__ __forceinline__ uint32_t stream_select(SelLds& L, const uint32_t* __r
       if (t.m & 16u) count(t.x);
     }
     wave_lds_sync();
-    wave_excl_prefix(L.hist, nblk, lane);
+    wave_excl_prefix32(L.hist, nblk, lane);
     wave_lds_sync();
     uint32_t x = 0;
     if (tl) {
@@ -555,14 +570,234 @@ __device__ __forceinline__ uint32_t row_select(SelLds& L, const uint32_t* __rest
     const uint32_t top = rs.rmax - rs.rmin - off;
     bits = top ? 32u - __clz(top) : 1u;
   }
-  const uint32_t kk = stream_select<NB>(L, samples, g, rs.rmin, off, bits, r, last, lane);
+  const uint32_t kk = stream_select(L, samples, g, rs.rmin, off, bits, r, last, lane);
   return (last ? kk + off : key) + rs.rmin;
 }
 
-// Samples per row handled by the NB-batch feature kernel: a row of N samples
-// needs ceil(floor(N / 4) / 256) batches at most.
+// ------------------------------------------------------- rows of any length
+// Rows longer than four load batches per lane (N > 4096 + 3) do not fit in
+// registers; one wave streams them in batches of 16 bytes x 4 per lane, the
+// next batch always in flight while the current one is summed.
+
+// Calls one(x) for every sample of batch u of a row (geometry g) that this
+// lane holds. A full batch and a batch without a head / tail sample are told
+// apart by wave-uniform tests, so only a partial batch pays a per-lane test.
+template <class One>
+__device__ __forceinline__ void for_batch(const Batch& B, const RowGeo& g, uint32_t u, One&& one) {
+  if ((u + 1u) * (4u * kWave) <= g.nq) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      one(B.q[q].x);
+      one(B.q[q].y);
+      one(B.q[q].z);
+      one(B.q[q].w);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if ((B.m >> q) & 1u) {
+        one(B.q[q].x);
+        one(B.q[q].y);
+        one(B.q[q].z);
+        one(B.q[q].w);
+      }
+  }
+  if (u + 1u == g.nb && (g.head | g.tail) != 0u && (B.m & 16u)) one(B.x);
+}
+
+// One row's results: minimum, maximum, moments (sum r; sum r^2 as 96 bits)
+// and, on lane j < RANKS::kCount, the sample of rank RANKS::rank(j, N).
+struct RowOut {
+  uint32_t rmin, rmax;
+  uint64_t s1, s2;
+  uint32_t s2h;
+  uint32_t sel;
+};
+
+// Lane j < RANKS::kCount: the sample of rank RANKS::rank(j, N), from the
+// window histogram in L of the keys r - base (every sample >= base).
+template <class RANKS>
+__device__ __forceinline__ uint32_t select_from_window(SelLds& L, const uint32_t* __restrict__ samples,
+                                                       const RowGeo& g, uint32_t base, uint32_t rmax, uint32_t N,
+                                                       uint32_t lane) {
+  uint32_t r;
+  bool last;
+  const uint32_t key = window_find<RANKS>(L, N, lane, r, last);
+  if (ballot(last) == 0) return key + base;
+  const uint32_t off = kSelWin - 1u;
+  const uint32_t top = rmax - base - off;
+  const uint32_t bits = top ? 32u - __clz(top) : 1u;
+  const uint32_t kk = stream_select(L, samples, g, base, off, bits, r, last, lane);
+  return (last ? kk + off : key) + base;
+}
+
+// The exact path for a long row the streaming pass could not finish (a
+// sample below the provisional base, or a range of 2^kFastBits or more): the
+// row is read again, its moments summed in 96 bits, its keys r - rmin counted
+// into a fresh window (unless the range needs all 32 bits), and the order
+// statistics selected.
+template <class RANKS>
+__device__ __forceinline__ void row_exact(SelLds& L, const uint32_t* __restrict__ samples, const RowGeo& g,
+                                          uint32_t N, uint32_t lane, RowOut& o) {
+  const uint32_t rmin = o.rmin;
+  const uint32_t range = o.rmax - rmin;
+  const uint32_t b = range ? 32u - __clz(range) : 0u;
+  u32x4* hv = reinterpret_cast<u32x4*>(L.hist);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) hv[lane * 4 + i] = u32x4{0u, 0u, 0u, 0u};
+  wave_lds_sync();
+  uint32_t unused = 0xffffffffu;
+  uint64_t s1 = 0, s2 = 0;
+  uint32_t s2h = 0;
+  const bool window = b >= 1 && b < 32;
+#pragma unroll 1
+  for (uint32_t u = 0; u < g.nb; ++u) {
+    Batch t;
+    load_batch(t, samples, g, u, lane);
+    for_batch(t, g, u, [&](uint32_t x) {
+      acc_sample(x, unused, s1, s2, s2h);
+      if (window) atomicAdd(&L.hist[min(x - rmin, kSelWin - 1u)], 1u);
+    });
+  }
+  wave_total_64_96(s1, s2, s2h);
+  o.s1 = s1;
+  o.s2 = s2;
+  o.s2h = s2h;
+  if (b == 0) {
+    o.sel = rmin;
+  } else if (window) {
+    o.sel = select_from_window<RANKS>(L, samples, g, rmin, o.rmax, N, lane);
+  } else {  // no window: radix levels over every key
+    const bool tl = lane < RANKS::kCount;
+    const uint32_t R = tl ? RANKS::rank(lane, N) : 0u;
+    o.sel = stream_select(L, samples, g, rmin, 0u, 32u, R, tl, lane) + rmin;
+  }
+}
+
+// Rows first, first + step, ... (below K) of a [K][N] block at element off0,
+// streamed by one wave; emit(i, o) receives each row's results. The two batch
+// buffers alternate, so no copy moves between them.
+//
+// Per row: the first batch's minimum m0, less a margin kSelMargin, is the
+// provisional base a; every sample then adds k = r - a to sums of k and k^2
+// (32-bit within a batch, 64-bit across batches; 24-bit multiplier) and
+// counts bin min(k, kSelWin - 1) of the window histogram. With the row's true
+// minimum m and maximum M at its end: if m >= a and M - a < 2^kFastBits, the
+// sums give sum r = sum k + N a and sum r^2 = sum k^2 + 2 a sum k + N a^2
+// exactly and the histogram (based at a) gives the order statistics;
+// otherwise row_exact reads the row again.
+constexpr uint32_t kSelMargin = 128;
+
+template <class RANKS, class Emit>
+__device__ __forceinline__ void select_rows_long(SelLds& L, const uint32_t* __restrict__ samples, uint64_t off0,
+                                                 uint32_t N, uint32_t K, uint32_t first, uint32_t step, uint32_t lane,
+                                                 Emit&& emit) {
+  struct Cursor {
+    uint32_t i, u;
+    RowGeo g;
+  };
+  auto geo = [&](uint32_t i) { return row_geo(samples, off0 + (uint64_t)i * N, N); };
+  auto advance = [&](const Cursor& c) {
+    Cursor n = c;
+    if (c.u + 1u < c.g.nb) {
+      n.u = c.u + 1u;
+    } else {
+      n.i = c.i + step;
+      n.u = 0;
+      if (n.i < K) n.g = geo(n.i);
+    }
+    return n;
+  };
+  // the row in progress
+  uint32_t base = 0, mn = 0, mx = 0;
+  uint64_t t1 = 0, t2 = 0;
+  uint32_t* hist = L.hist;
+  auto process = [&](const Batch& B, const Cursor& c) {
+    if (c.u == 0) {
+      // a new row: clear the window and take the provisional base from this batch
+      u32x4* hv = reinterpret_cast<u32x4*>(hist);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hv[lane * 4 + i] = u32x4{0u, 0u, 0u, 0u};
+      mn = 0xffffffffu;
+      mx = 0u;
+      for_batch(B, c.g, 0u, [&](uint32_t x) {
+        mn = min(mn, x);
+        mx = max(mx, x);
+      });
+      const uint32_t m0 = wave_min_u32(mn);
+      base = m0 > kSelMargin ? m0 - kSelMargin : 0u;
+      t1 = 0;
+      t2 = 0;
+      wave_lds_sync();
+    }
+    uint32_t t1b = 0, t2b = 0;
+    auto one = [&](uint32_t x) {
+      const uint32_t z = x - base;
+      t1b += z;
+      t2b = __umul24(z, z) + t2b;
+      atomicAdd(&hist[min(z, kSelWin - 1u)], 1u);
+    };
+    if (c.u == 0) {
+      for_batch(B, c.g, 0u, one);
+    } else {
+      for_batch(B, c.g, c.u, [&](uint32_t x) {
+        mn = min(mn, x);
+        mx = max(mx, x);
+        one(x);
+      });
+    }
+    t1 += t1b;
+    t2 += t2b;
+    if (c.u + 1u == c.g.nb) {  // the row's last batch
+      RowOut o;
+      o.rmin = wave_min_u32(mn);
+      o.rmax = wave_max_u32(mx);
+      if (o.rmin >= base && o.rmax - base < (1u << kFastBits)) {
+        uint64_t a1 = t1, a2 = t2;
+        uint32_t a2h = 0;
+        wave_total_64_96(a1, a2, a2h);
+        const u128 q2 = (((u128)a2h << 64) | a2) + (u128)(2ull * base) * a1 + (u128)((uint64_t)base * base) * N;
+        o.s1 = a1 + (uint64_t)base * N;
+        o.s2 = (uint64_t)q2;
+        o.s2h = (uint32_t)(q2 >> 64);
+        o.sel = o.rmax == o.rmin ? o.rmin : select_from_window<RANKS>(L, samples, c.g, base, o.rmax, N, lane);
+      } else {
+        row_exact<RANKS>(L, samples, c.g, N, lane, o);
+      }
+      emit(c.i, o);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  Cursor c;
+  c.i = first;
+  c.u = 0;
+  if (c.i >= K) return;
+  c.g = geo(c.i);
+  Batch A, B;
+  load_batch(A, samples, c.g, 0u, lane);
+  for (;;) {
+    Cursor n = advance(c);
+    if (n.i < K) load_batch(B, samples, n.g, n.u, lane);
+    process(A, c);
+    if (n.i >= K) break;
+    c = advance(n);
+    if (c.i < K) load_batch(A, samples, c.g, c.u, lane);
+    process(B, n);
+    if (c.i >= K) break;
+  }
+}
+
+// Row class of the order-statistics kernels: a row of N samples needs
+// ceil(floor(N / 4) / 256) load batches at most; rows of up to 1, 2 or 4 of
+// them are held in registers (class 1, 2, 4), longer rows are streamed
+// (class kStreamed).
+constexpr uint32_t kStreamed = 8;
 __host__ __device__ constexpr uint32_t feat_batches(uint32_t N) {
-  return (N / 4 + 4u * kWave - 1) / (4u * kWave) <= 1 ? 1u : ((N / 4 + 4u * kWave - 1) / (4u * kWave) <= 2 ? 2u : 4u);
+  return (N / 4 + 4u * kWave - 1) / (4u * kWave) <= 1
+             ? 1u
+             : ((N / 4 + 4u * kWave - 1) / (4u * kWave) <= 2
+                    ? 2u
+                    : ((N / 4 + 4u * kWave - 1) / (4u * kWave) <= 4 ? 4u : kStreamed));
 }
 
 }  // namespace ks

@@ -63,24 +63,31 @@ __global__ __launch_bounds__(256) void row_stats_kernel(const uint32_t* __restri
   }
   const uint32_t K = d.K, N = d.N;
   ks::SelLds& L = sel[w];
-  ks::Batch cur[NB];
-  ks::RowGeo g;
-  if (w < K) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)w * N, N, lane);
-  for (uint32_t i = w; i < K; i += W) {
-    uint64_t s1, s2;
-    uint32_t s2h;
-    const ks::RowScan rs = ks::row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
-    // the next row's loads are in flight while this row's percentiles are found
-    const ks::RowGeo gi = g;
-    if (i + W < K) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)(i + W) * N, N, lane);
-    const uint32_t sel_x = ks::row_select<NB, StatRanks>(L, samples, gi, rs, N, lane);
-    const uint32_t rmin = rs.rmin, rmax = rs.rmax;
+  auto emit = [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t rmin, uint32_t rmax, uint32_t sel_x) {
     const uint32_t p95 = (uint32_t)__builtin_amdgcn_readlane((int)sel_x, 1);
     if (lane == 0) {
       const u128 S2 = ((u128)s2h << 64) | s2;
       const u128 num = (u128)N * S2 - (u128)s1 * s1;  // >= 0 (Cauchy-Schwarz), < 2^113
       const double nn = (double)N * (double)N;
       o[i] = ks_row_stats{(double)s1 / (double)N, sqrt(u128_to_double(num) / nn), rmin, sel_x, p95, rmax};
+    }
+  };
+  if constexpr (NB == (int)ks::kStreamed) {
+    ks::select_rows_long<StatRanks>(L, samples, d.offset, N, K, w, W, lane, [&](uint32_t i, const ks::RowOut& r) {
+      emit(i, r.s1, r.s2, r.s2h, r.rmin, r.rmax, r.sel);
+    });
+  } else {
+    ks::Batch cur[NB];
+    ks::RowGeo g;
+    if (w < K) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)w * N, N, lane);
+    for (uint32_t i = w; i < K; i += W) {
+      uint64_t s1, s2;
+      uint32_t s2h;
+      const ks::RowScan rs = ks::row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
+      // the next row's loads are in flight while this row's percentiles are found
+      const ks::RowGeo gi = g;
+      if (i + W < K) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)(i + W) * N, N, lane);
+      emit(i, s1, s2, s2h, rs.rmin, rs.rmax, ks::row_select<NB, StatRanks>(L, samples, gi, rs, N, lane));
     }
   }
 }
@@ -97,7 +104,7 @@ extern "C" int ks_stats_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t num
   DeviceGuard g(ctx->device);
   if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  // one launch per row length class (1, 2 or 4 load batches per row); each
+  // one launch per row class (1, 2 or 4 load batches per row, or streamed); each
   // workgroup whose series belongs to another class returns at once
   hipLaunchKernelGGL(row_stats_kernel<1>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
                      max_K, out, out_rows);
@@ -105,6 +112,8 @@ extern "C" int ks_stats_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t num
                      max_K, out, out_rows);
   hipLaunchKernelGGL(row_stats_kernel<4>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
                      max_K, out, out_rows);
+  hipLaunchKernelGGL(row_stats_kernel<ks::kStreamed>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc,
+                     num_series, max_K, out, out_rows);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? KS_OK : hip_fail(e, "row stats launch");
 }

@@ -117,6 +117,45 @@ def _select_stress_series():
     return out
 
 
+def _long_row_series():
+    """Rows of more than 4096 + 3 samples (the streamed class): latency-like,
+    upper deciles past the unit-bin window, a full 32-bit range, a first batch
+    above the rest (the provisional base fails), constant rows, and rows of
+    more than 2^16 samples (32-bit counts in the radix levels)."""
+    rng = np.random.default_rng(20251106)
+    out = []
+    for N in (4100, 5003, 8195):
+        base = rng.lognormal(np.log(600), 0.08, (3, N))
+        out.append(np.round(base * np.where(rng.random((3, N)) < 0.02, rng.uniform(1, 5, (3, N)), 1.0)).astype(np.uint32))
+    heavy = rng.integers(2_000, 5_000_000, (2, 6001))
+    out.append(np.where(rng.random((2, 6001)) < 0.5, rng.integers(300, 340, (2, 6001)), 300 + heavy).astype(np.uint32))
+    out.append(rng.integers(0, 1 << 32, (2, 4500), dtype=np.uint64).astype(np.uint32))
+    r = rng.integers(90, 110, (2, 9000))
+    r[:, :1100] += 5000  # the first batch sits far above the rest of the row
+    out.append(r.astype(np.uint32))
+    out.append(np.full((2, 4097 + 7), 123456, np.uint32))
+    out.append(rng.integers(0, 1 << 32, (2, 70_001), dtype=np.uint64).astype(np.uint32))
+    out.append(np.round(rng.lognormal(np.log(300), 0.1, (2, 66_000))).astype(np.uint32))
+    return out
+
+
+def test_features_long_rows(ctx):
+    ss = _long_row_series()
+    parts, offs, off = [], [], 0
+    for r in ss:
+        off += 1
+        offs.append(off)
+        parts.append(np.zeros(1, np.uint32))
+        parts.append(r.ravel())
+        off += r.size
+    x = np.concatenate(parts)
+    d = P.make_desc(offs, [r.shape[0] for r in ss], [r.shape[1] for r in ss])
+    f = gpu_features(ctx, x, d, 64)
+    for t, r in enumerate(ss):
+        a = int(d[t]["aux_offset"])
+        assert np.array_equal(f[a:a + r.shape[0]], O.features(r)), (t, r.shape)
+
+
 def test_features_select_stress(ctx):
     ss = _select_stress_series()
     parts, offs, off = [], [], 0

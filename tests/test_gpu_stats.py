@@ -11,7 +11,7 @@ import oracle as O
 import paper_2511_05958_amd as P
 from paper_2511_05958_amd import synth as S
 
-from test_gpu_learned import _select_stress_series
+from test_gpu_learned import _long_row_series, _select_stress_series
 
 pytestmark = pytest.mark.gpu
 
@@ -66,11 +66,30 @@ def test_stats_every_class_alignment_and_range(ctx):
         assert same(g[a:a + r.shape[0]], O.row_stats(r)), (t, r.shape)
 
 
+def test_stats_long_rows(ctx):
+    """Rows longer than the register classes hold (streamed), every alignment,
+    through the window, past it, over all 32 bits and with counts above 2^16."""
+    ss = _long_row_series()
+    parts, offs, off = [], [], 0
+    for r in ss:
+        off += 3
+        offs.append(off)
+        parts.append(np.zeros(3, np.uint32))
+        parts.append(r.ravel())
+        off += r.size
+    x = np.concatenate(parts)
+    d = P.make_desc(offs, [r.shape[0] for r in ss], [r.shape[1] for r in ss])
+    g = gpu_stats(ctx, x, d, 64)
+    for t, r in enumerate(ss):
+        a = int(d[t]["aux_offset"])
+        assert same(g[a:a + r.shape[0]], O.row_stats(r)), (t, r.shape)
+
+
 def test_stats_malformed_series(ctx):
     b = S.make_batch(2, num_series=4, first_series=3)
     x = S.fill_host(b)
     d = P.make_desc(b.specs["offset"], b.specs["K"], b.specs["N"])
-    d[1]["N"] = 5000              # above KS_FEATURE_MAX_N
+    d[1]["N"] = 0                 # N < 1: a bad shape
     d[2]["offset"] = len(x)       # past the samples
     g = gpu_stats(ctx, x, d, 256)
     for t in (1, 2):
