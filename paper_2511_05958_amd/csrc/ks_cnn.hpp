@@ -145,6 +145,8 @@ __global__ __launch_bounds__(NTC) void conv_kernel(const uint16_t* __restrict__ 
 // them, and each output accumulates over j in the per-layer kernels' order
 // (same MFMA steps, bias added last). Wave w owns output channels 16w .. 16w + 15
 // of layers 0..2 and keeps their weights in registers for the whole launch.
+// A frame with no row inside a series (slot padding after a short series)
+// only writes its zero logits.
 constexpr int FT = 128;
 constexpr int FH = 8;
 constexpr int FR = FT + 2 * FH;  // 144
@@ -248,9 +250,19 @@ __global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(3))) void f
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = (int64_t)(tile * FT);
     __syncthreads();
+    int any = 0;
     for (uint32_t f = tid; f < (uint32_t)FR; f += NTC) {
       const int64_t row = r0 - FH + (int64_t)f;
-      sm.valid[f] = row >= 0 && row_valid((uint64_t)row, rows, SR, Ks);
+      const bool v = row >= 0 && row_valid((uint64_t)row, rows, SR, Ks);
+      sm.valid[f] = v;
+      any |= v;
+    }
+    if (!__syncthreads_or(any)) {
+      // no row of the frame lies in a series (slot padding past a short
+      // series): every activation is zero there, so every logit is 0
+      for (uint32_t f = tid; f < (uint32_t)FT; f += NTC)
+        if ((uint64_t)r0 + f < rows) logits[(uint64_t)r0 + f] = 0.0f;
+      continue;
     }
     for (uint32_t q = tid; q < 2u * FR; q += NTC) {
       const uint32_t f = q >> 1, h = q & 1u;
