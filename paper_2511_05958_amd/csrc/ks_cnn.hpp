@@ -159,15 +159,28 @@ struct FusedSmem {
   uint16_t act[2][(FR + 4) * FST];  // buffer row f + 2 holds frame row f; rows 0, 1, FR + 2, FR + 3 stay zero
   uint16_t x[(FR + 4) * FXS];
   uint16_t w3[2 * FW3];             // row 0: W3[0][j]; row 1: zeros (output channels 1..15)
-  uint8_t valid[FR];
+  uint64_t valid[4];                // bit f % 64 of word f / 64: frame row f lies inside a series
 };
+
+// Bits 4 b + e (b < FBLK, e < 4) of a lane's row mask: frame row 16 b + 4 kg + e
+// is valid (the rows whose outputs this lane holds in an MFMA result).
+__device__ __forceinline__ uint64_t fused_lane_rows(const uint64_t (&v)[3], uint32_t kg) {
+  uint64_t m = 0;
+#pragma unroll
+  for (int b = 0; b < FBLK; ++b) {
+    const int f0 = 16 * b;  // + 4 kg
+    const uint64_t word = v[f0 / 64];
+    m |= ((word >> ((f0 % 64) + 4 * kg)) & 0xFull) << (4 * b);
+  }
+  return m;
+}
 
 // One 64-output-channel layer over the frame for this wave's 16 channels:
 // out[f][16 w + m] = bf16(relu(b + sum_j W[16 w + m][j] in[f + k - 2][i])) on
 // valid rows, 0 elsewhere (j = k CIN + i).
 template <int CIN, int NQ>
 __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ in, int ist, const u32x4 (&B)[NQ],
-                                            float bias, uint16_t* __restrict__ out, const uint8_t* __restrict__ valid,
+                                            float bias, uint16_t* __restrict__ out, uint64_t rows,
                                             uint32_t w, uint32_t m, uint32_t kg) {
   constexpr int J = KW * CIN;
 #pragma unroll 1
@@ -203,7 +216,8 @@ __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ in, int
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int f = (g + t) * 16 + (int)kg * 4 + e;
-        out[(f + 2) * FST + w * 16 + m] = valid[f] ? f2bf(relu(acc[t][e] + bias)) : (uint16_t)0;
+        const bool v = (rows >> (4 * (g + t) + e)) & 1u;
+        out[(f + 2) * FST + w * 16 + m] = v ? f2bf(relu(acc[t][e] + bias)) : (uint16_t)0;
       }
   }
 }
@@ -223,13 +237,9 @@ __global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(3))) void f
   const uint32_t tid = threadIdx.x, lane = lane_id(), w = wave_id();
   const uint32_t m = lane & 15u, kg = lane >> 4;
   const uint32_t o = w * 16 + m;
-  // B operands of this wave's channels: W[o][32 q + 8 kg .. + 7]
-  u32x4 B0[3], B1[10], B2[10];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int j0 = q * 32 + (int)kg * 8;
-    B0[q] = j0 < 80 ? *reinterpret_cast<const u32x4*>(w0 + o * 80 + j0) : u32x4{0u, 0u, 0u, 0u};
-  }
+  // B operands of this wave's channels: W[o][32 q + 8 kg .. + 7]; layers 1 and
+  // 2 stay in registers, layer 0's (three k-steps) are read again per tile
+  u32x4 B1[10], B2[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) {
     B1[q] = *reinterpret_cast<const u32x4*>(w1 + o * 320 + q * 32 + kg * 8);
@@ -250,14 +260,12 @@ __global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(3))) void f
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t r0 = (int64_t)(tile * FT);
     __syncthreads();
-    int any = 0;
-    for (uint32_t f = tid; f < (uint32_t)FR; f += NTC) {
-      const int64_t row = r0 - FH + (int64_t)f;
-      const bool v = row >= 0 && row_valid((uint64_t)row, rows, SR, Ks);
-      sm.valid[f] = v;
-      any |= v;
-    }
-    if (!__syncthreads_or(any)) {
+    // frame row f = tid (FR <= NTC): its validity as one bit per row, by ballot
+    const int64_t vrow = r0 - FH + (int64_t)tid;
+    const bool v = tid < (uint32_t)FR && vrow >= 0 && row_valid((uint64_t)vrow, rows, SR, Ks);
+    const uint64_t vb = ballot(v);
+    if (lane == 0) sm.valid[w] = vb;
+    if (!__syncthreads_or(v)) {
       // no row of the frame lies in a series (slot padding past a short
       // series): every activation is zero there, so every logit is 0
       for (uint32_t f = tid; f < (uint32_t)FT; f += NTC)
@@ -272,11 +280,23 @@ __global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(3))) void f
       *reinterpret_cast<u32x4*>(&sm.x[(f + 2) * FXS + h * 8]) = v;
     }
     __syncthreads();
-    fused_layer<16, 3>(sm.x, FXS, B0, bias0, sm.act[0], sm.valid, w, m, kg);
+    const uint64_t vw[3] = {sm.valid[0], sm.valid[1], sm.valid[2]};
+    const uint64_t lrows = fused_lane_rows(vw, kg);
+    u32x4 B0[3];
+    {
+      const uint16_t* w0p = w0;
+      asm volatile("" : "+v"(w0p));  // read per tile: keeps the compiler from pinning B0 in registers
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int j0 = q * 32 + (int)kg * 8;
+        B0[q] = j0 < 80 ? *reinterpret_cast<const u32x4*>(w0p + o * 80 + j0) : u32x4{0u, 0u, 0u, 0u};
+      }
+    }
+    fused_layer<16, 3>(sm.x, FXS, B0, bias0, sm.act[0], lrows, w, m, kg);
     __syncthreads();
-    fused_layer<64, 10>(sm.act[0], FST, B1, bias1, sm.act[1], sm.valid, w, m, kg);
+    fused_layer<64, 10>(sm.act[0], FST, B1, bias1, sm.act[1], lrows, w, m, kg);
     __syncthreads();
-    fused_layer<64, 10>(sm.act[1], FST, B2, bias2, sm.act[0], sm.valid, w, m, kg);
+    fused_layer<64, 10>(sm.act[1], FST, B2, bias2, sm.act[0], lrows, w, m, kg);
     __syncthreads();
     // last layer (one output channel): wave w takes row blocks w, w + 4, w + 8
     const uint16_t* w3row = &sm.w3[m == 0 ? 0 : FW3];
@@ -303,7 +323,7 @@ __global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(3))) void f
         for (int e = 0; e < 4; ++e) {
           const int f = blk * 16 + (int)kg * 4 + e;
           const int64_t row = r0 - FH + f;
-          if (f >= FH && f < FH + FT && (uint64_t)row < rows) logits[row] = sm.valid[f] ? acc[e] + bias3 : 0.0f;
+          if (f >= FH && f < FH + FT && (uint64_t)row < rows) logits[row] = ((lrows >> (4 * blk + e)) & 1u) ? acc[e] + bias3 : 0.0f;
         }
       }
     }
