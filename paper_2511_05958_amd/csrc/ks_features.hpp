@@ -88,51 +88,63 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 
   }
 }
 
-// Second step, one workgroup per series, every slot row r on its own thread:
-// the deciles x of the series' rows become the features
-// f = (double)(x - m) / max(m, 1) rounded to float (m the series minimum), in
-// place and into the caller's buffer, and the network input row (bf16 of the
-// nine features and the two position channels; channels 11..15 zero) is
-// written; slot rows outside [2, 2 + K) (the convolutions' zero padding) and
-// every row of a malformed series (K = 0) are zero.
+// Second step, one workgroup per (series, chunk of NT slot rows): the deciles
+// x of the series' rows become the features f = (double)(x - m) / max(m, 1)
+// rounded to float (m the series minimum), in place and into the caller's
+// buffer, element by element (consecutive threads, consecutive elements);
+// then the chunk's network input rows (bf16 of the nine features and the two
+// position channels, channels 11..15 zero), staged in LDS, are written as
+// 16-byte stores. Slot rows outside [2, 2 + K) (the convolutions' zero
+// padding) and every row of a malformed series (K = 0) are zero.
 template <int NT>
 __global__ __launch_bounds__(NT) void feature_pack_kernel(const ks_desc* __restrict__ desc, uint32_t num_series,
                                                           float* __restrict__ feat_out, uint64_t feat_rows,
                                                           uint16_t* __restrict__ x0, uint32_t SR, LearnWs lw,
                                                           float* __restrict__ feat_ws) {
+  __shared__ __align__(16) uint16_t bf[NT * 16];
   const uint32_t s = blockIdx.x;
   if (s >= num_series) return;
-  const uint32_t r = blockIdx.y * NT + threadIdx.x;
-  if (r >= SR) return;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t r0 = blockIdx.y * NT;
+  if (r0 >= SR) return;
+  const uint32_t nr = SR - r0 < (uint32_t)NT ? SR - r0 : (uint32_t)NT;
   const uint32_t K = lw.K[s];
-  const uint64_t row = (uint64_t)s * SR + r;
-  u32x4 lo{0u, 0u, 0u, 0u}, hi{0u, 0u, 0u, 0u};
-  if (r >= 2 && r < K + 2) {
+  const uint64_t row0 = (uint64_t)s * SR + r0;
+  // rows [lo, hi) of the chunk hold data
+  const uint32_t lo = r0 < 2u ? 2u - r0 : 0u;
+  const uint32_t hi = K + 2u > r0 ? (K + 2u - r0 < nr ? K + 2u - r0 : nr) : 0u;
+  if (lo < hi) {
     const uint32_t gmin = lw.smin[s];
     const double denom = (double)(gmin > 1 ? gmin : 1u);
     const ks_desc d = desc[s];
     const bool to_user = feat_out && d.aux_offset <= feat_rows && K <= feat_rows - d.aux_offset;
-    uint16_t b[16];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const uint32_t x = __float_as_uint(feat_ws[row * 9 + k]);
+    for (uint32_t q = lo * 9u + tid; q < hi * 9u; q += NT) {
+      const uint32_t rr = q / 9u, k = q - rr * 9u;
+      const uint64_t e = row0 * 9u + q;
+      const uint32_t x = __float_as_uint(feat_ws[e]);
       const float f = (float)((double)(x - gmin) / denom);
-      feat_ws[row * 9 + k] = f;
-      if (to_user) feat_out[(d.aux_offset + r - 2) * 9 + k] = f;
-      b[k] = cnn::f2bf(f);
+      feat_ws[e] = f;
+      if (to_user) feat_out[(d.aux_offset + r0 + rr - 2) * 9 + k] = f;
+      bf[rr * 16 + k] = cnn::f2bf(f);
     }
-    b[9] = cnn::f2bf(cnn::pos_frac(r - 2, K));
-    b[10] = cnn::f2bf(cnn::pos_centre(r - 2, K));
-#pragma unroll
-    for (int k = 11; k < 16; ++k) b[k] = 0;
-    lo = u32x4{b[0] | ((uint32_t)b[1] << 16), b[2] | ((uint32_t)b[3] << 16), b[4] | ((uint32_t)b[5] << 16),
-               b[6] | ((uint32_t)b[7] << 16)};
-    hi = u32x4{b[8] | ((uint32_t)b[9] << 16), b[10] | ((uint32_t)b[11] << 16), b[12] | ((uint32_t)b[13] << 16),
-               b[14] | ((uint32_t)b[15] << 16)};
   }
-  u32x4* dst = reinterpret_cast<u32x4*>(x0 + row * 16);
-  dst[0] = lo;
-  dst[1] = hi;
+  __syncthreads();
+  for (uint32_t q = tid; q < nr * 2u; q += NT) {
+    const uint32_t rr = q >> 1, h = q & 1u;
+    u32x4 v{0u, 0u, 0u, 0u};
+    if (rr >= lo && rr < hi) {
+      const uint32_t t = r0 + rr - 2;
+      if (h == 0) {
+        const u32x4 a = *reinterpret_cast<const u32x4*>(&bf[rr * 16]);
+        v = a;
+      } else {
+        const uint32_t b8 = bf[rr * 16 + 8];
+        const uint32_t p9 = cnn::f2bf(cnn::pos_frac(t, K)), p10 = cnn::f2bf(cnn::pos_centre(t, K));
+        v = u32x4{b8 | (p9 << 16), p10, 0u, 0u};
+      }
+    }
+    *reinterpret_cast<u32x4*>(x0 + (row0 + rr) * 16 + h * 8) = v;
+  }
 }
 
 }  // namespace ks
