@@ -22,22 +22,70 @@ struct LearnWs {
   uint32_t* K;      // [num_series]: K when the series was valid, 0 otherwise
 };
 
-// First step, one series per workgroup (series of row class NB: rows in 1,
-// 2 or 4 load batches held in registers, or kStreamed; the NB = 1 launch also
-// marks malformed series with K = 0). One wave per row, rows w, w + 4, ...
-// for wave w. Writes per row the deciles (as raw samples, at row slot
-// s * SR + 2 + i of feat_ws) and the refine workspace's moments, and per
-// series its minimum and K.
+// Series order of the feature pass (one workgroup): per row class (1, 2 or 4
+// load batches, or streamed) the series largest first, bucketed by the bit
+// length of their sample bytes (a longest-processing-time order, so a
+// class's launch starts its longest workgroups first and no workgroup waits
+// behind a class it does not belong to); malformed series last in class 1.
+// plan[0 .. n) is the order, plan[n + c] the first index of class c and
+// plan[n + 4 + c] its count.
+constexpr int kFeatPlanNT = 1024;
+constexpr uint32_t kFeatBuckets = 40;
+
+__device__ __forceinline__ uint32_t feat_class_index(uint32_t NB) {
+  return NB == 1 ? 0u : (NB == 2 ? 1u : (NB == 4 ? 2u : 3u));
+}
+
+__global__ __launch_bounds__(kFeatPlanNT) void feature_plan_kernel(const ks_desc* __restrict__ desc,
+                                                                   uint32_t num_series, uint64_t num_samples,
+                                                                   uint32_t max_K, uint32_t* __restrict__ plan) {
+  __shared__ uint32_t cnt[4 * kFeatBuckets];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < 4 * kFeatBuckets; i += kFeatPlanNT) cnt[i] = 0;
+  __syncthreads();
+  auto key = [&](uint32_t s) -> uint32_t {
+    const ks_desc d = desc[s];
+    if (check_desc(d, num_samples, max_K) || d.N > KS_FEATURE_MAX_N) return kFeatBuckets - 1;
+    const uint64_t bytes = 4ull * d.K * d.N;  // < 2^38
+    const uint32_t bl = 64u - (uint32_t)__clzll(bytes);
+    return feat_class_index(feat_batches(d.N)) * kFeatBuckets + (kFeatBuckets - 2 - min(bl, kFeatBuckets - 2));
+  };
+  for (uint32_t s = tid; s < num_series; s += kFeatPlanNT) atomicAdd(&cnt[key(s)], 1u);
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (uint32_t c = 0; c < 4; ++c) {
+      plan[num_series + c] = run;
+      for (uint32_t b = 0; b < kFeatBuckets; ++b) {
+        const uint32_t k = cnt[c * kFeatBuckets + b];
+        cnt[c * kFeatBuckets + b] = run;
+        run += k;
+      }
+      plan[num_series + 4 + c] = run - plan[num_series + c];
+    }
+  }
+  __syncthreads();
+  for (uint32_t s = tid; s < num_series; s += kFeatPlanNT) plan[atomicAdd(&cnt[key(s)], 1u)] = s;
+}
+
+// First step, workgroup t of the launch of row class NB (rows in 1, 2 or 4
+// load batches held in registers, or kStreamed) takes the t-th series of that
+// class in the plan's order (the NB = 1 launch also marks malformed series
+// with K = 0). One wave per row, rows w, w + 4, ... for wave w. Writes per row
+// the deciles (as raw samples, at row slot s * SR + 2 + i of feat_ws) and the
+// refine workspace's moments, and per series its minimum and K.
 template <int NB, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 : 1))) void features_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                       const ks_desc* __restrict__ desc, uint32_t num_series,
                                                       uint32_t max_K, uint32_t SR, LearnWs lw,
-                                                      float* __restrict__ feat_ws) {
+                                                      float* __restrict__ feat_ws,
+                                                      const uint32_t* __restrict__ plan) {
   constexpr int W = NT / kWave;
   __shared__ SelLds sel[W];
   __shared__ uint32_t red[W];
-  const uint32_t s = blockIdx.x;
-  if (s >= num_series) return;
+  const uint32_t ci = feat_class_index(NB);
+  if (blockIdx.x >= plan[num_series + 4 + ci]) return;
+  const uint32_t s = plan[plan[num_series + ci] + blockIdx.x];
   const ks_desc d = desc[s];
   const uint32_t tid = threadIdx.x, lane = lane_id();
   const uint32_t w = wave_id();
