@@ -156,6 +156,36 @@ def test_features_long_rows(ctx):
         assert np.array_equal(f[a:a + r.shape[0]], O.features(r)), (t, r.shape)
 
 
+def test_features_every_class_in_one_call(ctx):
+    """One call whose series fall in all four row classes (1, 2 or 4 load batches,
+    streamed) plus malformed ones, interleaved: the per-class plan must hand
+    every valid series to exactly one launch."""
+    import torch
+
+    rng = np.random.default_rng(7)
+    Ns = [900, 4500, 1500, 3000, 60, 2051, 4099, 4100, 1027, 1028, 9000]
+    ss = [np.round(rng.lognormal(np.log(400 + 50 * t), 0.08, (2 + t % 4, N))).astype(np.uint32)
+          for t, N in enumerate(Ns)]
+    parts, offs, off = [], [], 0
+    for r in ss:
+        off += 2
+        offs.append(off)
+        parts.append(np.zeros(2, np.uint32))
+        parts.append(r.ravel())
+        off += r.size
+    x = np.concatenate(parts)
+    d = P.make_desc(offs, [r.shape[0] for r in ss], [r.shape[1] for r in ss])
+    d[3]["N"] = 0            # malformed: N < 1
+    d[8]["offset"] = len(x)  # malformed: past the samples
+    f = gpu_features(ctx, x, d, 64)
+    for t, r in enumerate(ss):
+        a = int(d[t]["aux_offset"])
+        if t in (3, 8):
+            assert np.isnan(f[a:a + r.shape[0]]).all(), t  # skipped: the caller's rows stay untouched
+        else:
+            assert np.array_equal(f[a:a + r.shape[0]], O.features(r)), (t, r.shape)
+
+
 def test_features_select_stress(ctx):
     ss = _select_stress_series()
     parts, offs, off = [], [], 0
