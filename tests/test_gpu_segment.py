@@ -114,6 +114,49 @@ def test_levels_limit_and_level_one_is_the_plain_scan(ctx):
         check_series(cps2[t], int(counts2[t]), ref, t)
 
 
+@pytest.mark.parametrize("max_levels", [0, 1, 3, 4, 5, 6, 9, 13])
+def test_deep_recursion_level_limits(ctx, max_levels):
+    """Geometric staircases (plateaus of 256, 128, 64, ... rows) recurse about
+    eight depths deep on one side; limits around the host's read-back chunks
+    (depths 1-4, 5-12, 13-28) must cut exactly where the oracle's recursion does."""
+    rng = np.random.default_rng(99)
+    K, N = 512, 64
+    ss = []
+    for t in range(6):
+        edges = [0] + [K - (K >> (j + 1)) for j in range(9)] + [K]
+        lv = np.zeros(K)
+        for j in range(len(edges) - 1):
+            lv[edges[j]:edges[j + 1]] = 200 + 120 * j * (1 + 0.1 * t)
+        r = np.round(lv[:, None] * rng.lognormal(0, 0.01 * (t % 3), (K, N)))
+        ss.append(r.astype(np.uint32))
+    b = S.make_batch(3, num_series=10, first_series=700)
+    x3 = S.fill_host(b)
+    parts, offs, Ks, Ns, off = [], [], [], [], 0
+    for r in ss:
+        offs.append(off)
+        Ks.append(r.shape[0])
+        Ns.append(r.shape[1])
+        parts.append(r.ravel())
+        off += r.size
+    for t in range(10):
+        o, k, n = int(b.specs["offset"][t]), int(b.specs["K"][t]), int(b.specs["N"][t])
+        offs.append(off)
+        Ks.append(k)
+        Ns.append(n)
+        parts.append(x3[o:o + k * n])
+        off += k * n
+    x = np.concatenate(parts)
+    d = P.make_desc(offs, Ks, Ns)
+    cps, counts = run(ctx, x, d, 512, max_levels=max_levels)
+    deepest = 0
+    for t in range(len(d)):
+        ref = O.segment(series(x, d, t), max_levels=max_levels)
+        check_series(cps[t], int(counts[t]), ref, t)
+        deepest = max([deepest] + [r["depth"] for r in ref])
+    if max_levels == 0:
+        assert deepest >= 6  # the staircases recurse into the second read-back chunk (depths 5-12)
+
+
 def test_truncation_and_malformed_descriptors(ctx):
     b = S.make_batch(2, num_series=8, first_series=7)
     x = S.fill_host(b)
