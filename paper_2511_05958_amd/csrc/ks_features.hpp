@@ -68,10 +68,23 @@ __global__ __launch_bounds__(kFeatPlanNT) void feature_plan_kernel(const ks_desc
   for (uint32_t s = tid; s < num_series; s += kFeatPlanNT) plan[atomicAdd(&cnt[key(s)], 1u)] = s;
 }
 
+// Per-wave staging of a wave's per-row outputs: a wave takes a contiguous
+// block of rows and writes every kFeatStage rows' deciles and moments as
+// contiguous stores (rows written one at a time, by waves interleaved row by
+// row, left partly written cache lines behind; they cost 5 - 15% of the
+// pass and made its time depend on where the buffers lay in memory).
+constexpr uint32_t kFeatStage = 16;
+struct FeatStage {
+  uint32_t dec[kFeatStage * 9];
+  uint64_t s1[kFeatStage], s2lo[kFeatStage];
+  uint32_t s2hi[kFeatStage];
+};
+
 // First step, workgroup t of the launch of row class NB (rows in 1, 2 or 4
 // load batches held in registers, or kStreamed) takes the t-th series of that
 // class in the plan's order (the NB = 1 launch also marks malformed series
-// with K = 0). One wave per row, rows w, w + 4, ... for wave w. Writes per row
+// with K = 0). One wave per row; wave w takes rows [w B, (w + 1) B) with
+// B = ceil(K / 4). Writes per row
 // the deciles (as raw samples, at row slot s * SR + 2 + i of feat_ws) and the
 // refine workspace's moments, and per series its minimum and K.
 template <int NB, int NT>
@@ -82,6 +95,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 
                                                       const uint32_t* __restrict__ plan) {
   constexpr int W = NT / kWave;
   __shared__ SelLds sel[W];
+  __shared__ FeatStage stage[W];
   __shared__ uint32_t red[W];
   const uint32_t ci = feat_class_index(NB);
   if (blockIdx.x >= plan[num_series + 4 + ci]) return;
@@ -98,31 +112,47 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 
   const uint32_t K = d.K, N = d.N;
   const uint64_t slot = (uint64_t)s * SR + 2;
   SelLds& L = sel[w];
+  FeatStage& st = stage[w];
+  const uint32_t B = (K + W - 1) / W;
+  const uint32_t begin = min(w * B, K), end = min(begin + B, K);
   uint32_t gmin = 0xffffffffu;
   auto emit = [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t rmin, uint32_t dec) {
+    const uint32_t j = (i - begin) % kFeatStage;
     if (lane == 0) {
-      lw.s1[slot + i] = s1;
-      lw.s2lo[slot + i] = s2;
-      lw.s2hi[slot + i] = s2h;
+      st.s1[j] = s1;
+      st.s2lo[j] = s2;
+      st.s2hi[j] = s2h;
     }
     gmin = min(gmin, rmin);
     // feature numerators x - m need the series minimum: keep x itself
-    if (lane < 9) feat_ws[(slot + i) * 9 + lane] = __uint_as_float(dec);
+    if (lane < 9) st.dec[j * 9 + lane] = dec;
+    if (j + 1 == kFeatStage || i + 1 == end) {  // flush rows i - j .. i
+      wave_lds_sync();
+      const uint64_t r0 = slot + i - j;
+      for (uint32_t q = lane; q < (j + 1) * 9; q += kWave)
+        __builtin_nontemporal_store(__uint_as_float(st.dec[q]), &feat_ws[r0 * 9 + q]);
+      if (lane <= j) {
+        __builtin_nontemporal_store(st.s1[lane], &lw.s1[r0 + lane]);
+        __builtin_nontemporal_store(st.s2lo[lane], &lw.s2lo[r0 + lane]);
+        __builtin_nontemporal_store(st.s2hi[lane], &lw.s2hi[r0 + lane]);
+      }
+      wave_lds_sync();
+    }
   };
   if constexpr (NB == (int)kStreamed) {
-    select_rows_long<DecileRanks>(L, samples, d.offset, N, K, w, W, lane,
+    select_rows_long<DecileRanks>(L, samples, d.offset, N, end, begin, 1u, lane,
                                   [&](uint32_t i, const RowOut& o) { emit(i, o.s1, o.s2, o.s2h, o.rmin, o.sel); });
   } else {
     Batch cur[NB];
     RowGeo g;
-    if (w < K) g = load_row<NB>(cur, samples, d.offset + (uint64_t)w * N, N, lane);
-    for (uint32_t i = w; i < K; i += W) {
+    if (begin < end) g = load_row<NB>(cur, samples, d.offset + (uint64_t)begin * N, N, lane);
+    for (uint32_t i = begin; i < end; ++i) {
       uint64_t s1, s2;
       uint32_t s2h;
       const RowScan rs = row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
       // the next row's loads are in flight while this row's order statistics are found
       const RowGeo gi = g;
-      if (i + W < K) g = load_row<NB>(cur, samples, d.offset + (uint64_t)(i + W) * N, N, lane);
+      if (i + 1 < end) g = load_row<NB>(cur, samples, d.offset + (uint64_t)(i + 1) * N, N, lane);
       emit(i, s1, s2, s2h, rs.rmin, row_select<NB, DecileRanks>(L, samples, gi, rs, N, lane));
     }
   }

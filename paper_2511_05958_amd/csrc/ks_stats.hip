@@ -47,7 +47,9 @@ __global__ __launch_bounds__(256) void row_stats_kernel(const uint32_t* __restri
                                                         uint32_t max_K, ks_row_stats* __restrict__ out,
                                                         uint64_t out_rows) {
   constexpr int W = 4;
+  constexpr uint32_t kStage = 16;  // rows per contiguous write of a wave's records
   __shared__ ks::SelLds sel[W];
+  __shared__ __align__(16) uint32_t stage[W][kStage * 8];
   const uint32_t s = blockIdx.x;
   if (s >= num_series) return;
   const ks_desc d = desc[s];
@@ -63,30 +65,45 @@ __global__ __launch_bounds__(256) void row_stats_kernel(const uint32_t* __restri
   }
   const uint32_t K = d.K, N = d.N;
   ks::SelLds& L = sel[w];
+  // wave w takes rows [w B, (w + 1) B) and writes every kStage rows' records as
+  // contiguous 16-byte stores (records written one at a time, by waves
+  // interleaved row by row, left partly written cache lines behind)
+  const uint32_t B = (K + W - 1) / W;
+  const uint32_t begin = min(w * B, K), end = min(begin + B, K);
+  uint32_t* st = stage[w];
   auto emit = [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t rmin, uint32_t rmax, uint32_t sel_x) {
     const uint32_t p95 = (uint32_t)__builtin_amdgcn_readlane((int)sel_x, 1);
+    const uint32_t j = (i - begin) % kStage;
     if (lane == 0) {
       const u128 S2 = ((u128)s2h << 64) | s2;
       const u128 num = (u128)N * S2 - (u128)s1 * s1;  // >= 0 (Cauchy-Schwarz), < 2^113
       const double nn = (double)N * (double)N;
-      o[i] = ks_row_stats{(double)s1 / (double)N, sqrt(u128_to_double(num) / nn), rmin, sel_x, p95, rmax};
+      const ks_row_stats r{(double)s1 / (double)N, sqrt(u128_to_double(num) / nn), rmin, sel_x, p95, rmax};
+      *reinterpret_cast<ks_row_stats*>(st + j * 8) = r;
+    }
+    if (j + 1 == kStage || i + 1 == end) {  // flush rows i - j .. i
+      ks::wave_lds_sync();
+      if (lane < 2 * (j + 1))
+        __builtin_nontemporal_store(reinterpret_cast<const ks::u32x4*>(st)[lane],
+                                    &reinterpret_cast<ks::u32x4*>(o + (i - j))[lane]);
+      ks::wave_lds_sync();
     }
   };
   if constexpr (NB == (int)ks::kStreamed) {
-    ks::select_rows_long<StatRanks>(L, samples, d.offset, N, K, w, W, lane, [&](uint32_t i, const ks::RowOut& r) {
+    ks::select_rows_long<StatRanks>(L, samples, d.offset, N, end, begin, 1u, lane, [&](uint32_t i, const ks::RowOut& r) {
       emit(i, r.s1, r.s2, r.s2h, r.rmin, r.rmax, r.sel);
     });
   } else {
     ks::Batch cur[NB];
     ks::RowGeo g;
-    if (w < K) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)w * N, N, lane);
-    for (uint32_t i = w; i < K; i += W) {
+    if (begin < end) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)begin * N, N, lane);
+    for (uint32_t i = begin; i < end; ++i) {
       uint64_t s1, s2;
       uint32_t s2h;
       const ks::RowScan rs = ks::row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
       // the next row's loads are in flight while this row's percentiles are found
       const ks::RowGeo gi = g;
-      if (i + W < K) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)(i + W) * N, N, lane);
+      if (i + 1 < end) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)(i + 1) * N, N, lane);
       emit(i, s1, s2, s2h, rs.rmin, rs.rmax, ks::row_select<NB, StatRanks>(L, samples, gi, rs, N, lane));
     }
   }
