@@ -1,8 +1,9 @@
 // Order statistics of rows of uint32 samples, one wave per row: the row held
-// in registers (1, 2 or 4 load batches), its minimum and maximum by DPP, its
-// moments (sum r, sum r^2) fused with a histogram of its keys, and a
-// multi-rank select for up to nine target ranks. Used by the learned path's
-// decile features and by the per-row latency statistics.
+// in registers (1, 2 or 4 load batches per lane) or, for longer rows, streamed
+// in batches; its minimum and maximum by DPP, its moments (sum r, sum r^2)
+// fused with a histogram of its keys, and a multi-rank select for up to nine
+// target ranks. Used by the learned path's decile features and by the per-row
+// latency statistics.
 #pragma once
 
 #include "ks_scan.hpp"
@@ -12,7 +13,8 @@ namespace ks {
 
 // ------------------------------------------------------------------ deciles
 // Up to nine order statistics of one row, found by one wave with no block
-// barrier, over the keys r - row minimum.
+// barrier, over the keys r - base (the row minimum, or a provisional base at
+// or below it).
 //
 // Window level. One histogram pass with one bin per key value below
 // kSelWin - 1 and a last bin for every larger key: order statistics of latency
@@ -24,18 +26,21 @@ namespace ks {
 //
 // Radix levels, for targets that fall into the last bin (and for rows whose
 // range needs all 32 bits): an MSD radix select over the keys of that bin.
-// radix_select keeps the keys in registers (key arrays of the workflow
-// checks); stream_select reads a row again from memory at every level, so
-// that the row pass keeps no copy of the row for this rare case. Level 0 histograms the top kSelW0 bits of every key; each later
-// level histograms the next kSelW bits of only the keys that share a target's
-// prefix so far. Those keys form at most nine groups (one per distinct prefix
-// among the targets), numbered in target order. After each level every key is
-// rewritten in place as (group << s) | (its s low bits), s the bits still
-// unresolved, with group kSelNone for keys outside every group, so the next
-// level's bin is the key shifted right by the next s. Histograms are LDS
-// counters per (group, digit) bin; keys whose bin lies past the live groups
-// issue no LDS access (such keys would pile onto a few addresses and serialise
-// the atomics).
+// Level 0 histograms the top kSelW0 bits of every key; each later level
+// histograms the next kSelW bits of only the keys that share a target's prefix
+// so far. Those keys form at most nine groups (one per distinct prefix among
+// the targets), numbered in target order; histograms are LDS counters per
+// (group, digit) bin. Two forms:
+//   radix_select  keeps the keys in registers (the key arrays of the workflow
+//                 checks) and rewrites each key after a level as
+//                 (group << s) | (its s low bits), s the bits still unresolved,
+//                 with group kSelNone for keys outside every group, so the next
+//                 level's bin is one shift; keys past the live groups issue no
+//                 LDS access (they would pile onto a few addresses);
+//   stream_select reads the row again from memory at every level and finds a
+//                 key's group by comparing its prefix with the groups'
+//                 prefixes, so the row pass keeps no copy of the row for this
+//                 rare case.
 
 constexpr uint32_t kSelWin = 1024; // bins of the window level: keys 0 .. 1022 one each, 1023 the rest
 constexpr uint32_t kSelW0 = 10;    // bits of the level-0 digit (1024 bins fit the histogram)
