@@ -214,7 +214,7 @@ __device__ __forceinline__ uint32_t window_find(SelLds& L, uint32_t N, uint32_t 
   for (uint32_t j = 0; j < RANKS::kCount; ++j) {
     const uint32_t Rj = RANKS::rank(j, N);
     const uint64_t m = ballot(incl > Rj);  // not empty: Rj < N, the total
-    const uint32_t o = m ? (uint32_t)__builtin_ctzll(m) : kWave - 1u;
+    const uint32_t o = (uint32_t)__builtin_ctzll(m);
     if (lane == j) {
       owner = o;
       R = Rj;
@@ -225,27 +225,25 @@ __device__ __forceinline__ uint32_t window_find(SelLds& L, uint32_t N, uint32_t 
   r = 0;
   last = false;
   if (tl) {
-    r = R - below;  // rank within the owner's 16 bins
-    uint32_t bin = owner * 16u;
-    bool found = false;
+    // rank r within the owner's 16 bins: its bin is the number of bins whose
+    // inclusive count is <= r (branch-free: one compare and two selects per bin)
+    r = R - below;
+    uint32_t cum = 0, nb = 0, under = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const u32x4 q = hv[owner * 4 + i];
       const uint32_t c[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        if (!found) {
-          if (r < c[e]) {
-            found = true;
-          } else {
-            r -= c[e];
-            ++bin;
-          }
-        }
+        cum += c[e];
+        const bool le = cum <= r;
+        nb += le ? 1u : 0u;
+        under = le ? cum : under;
       }
     }
-    key = bin;
-    last = bin == kSelWin - 1u;  // keys >= kSelWin - 1: rank r among them
+    key = owner * 16u + nb;
+    r -= under;
+    last = key == kSelWin - 1u;  // keys >= kSelWin - 1: rank r among them
   }
   wave_lds_sync();
   return key;
