@@ -337,6 +337,36 @@ __device__ __forceinline__ void wave_total_32_64(uint32_t& a, uint64_t& c) {
   c = ((uint64_t)hi << 32) | lo;
 }
 
+// The same for a < 2^26 and c < 2^48 per lane (the fast moments of a row
+// held in registers: at most 68 keys below 2^13 per lane): c is reduced as its
+// low 16 bits and the rest, whose wave totals each fit 32 bits, so every step
+// is a 32-bit DPP add.
+__device__ __forceinline__ void wave_total_fast_moments(uint32_t& a, uint64_t& c) {
+  uint32_t lo = (uint32_t)c & 0xffffu, hi = (uint32_t)(c >> 16);
+  a += dpp<kDppXor1>(a);
+  lo += dpp<kDppXor1>(lo);
+  hi += dpp<kDppXor1>(hi);
+  a += dpp<kDppXor2>(a);
+  lo += dpp<kDppXor2>(lo);
+  hi += dpp<kDppXor2>(hi);
+  a += dpp<kDppHalfMirror>(a);
+  lo += dpp<kDppHalfMirror>(lo);
+  hi += dpp<kDppHalfMirror>(hi);
+  a += dpp<kDppMirror>(a);
+  lo += dpp<kDppMirror>(lo);
+  hi += dpp<kDppMirror>(hi);
+  a += dpp<kDppBcast15, 0xA>(a);
+  lo += dpp<kDppBcast15, 0xA>(lo);
+  hi += dpp<kDppBcast15, 0xA>(hi);
+  a += dpp<kDppBcast31, 0xC>(a);
+  lo += dpp<kDppBcast31, 0xC>(lo);
+  hi += dpp<kDppBcast31, 0xC>(hi);
+  a = (uint32_t)__builtin_amdgcn_readlane((int)a, 63);
+  lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
+  hi = (uint32_t)__builtin_amdgcn_readlane((int)hi, 63);
+  c = (uint64_t)lo + ((uint64_t)hi << 16);
+}
+
 // Largest row range bit length for which n keys k < 2^b have sum k^2 < 2^32
 // (and k < 2^24, the 24-bit multiplier's operand range).
 __host__ __device__ constexpr uint32_t fast_moment_bits(uint32_t n) {
@@ -435,7 +465,7 @@ __device__ __forceinline__ RowScan row_scan(SelLds& L, const Batch (&B)[NB], con
           t2 += t2b;
           t2b = 0;
         });
-    wave_total_32_64(t1, t2);
+    wave_total_fast_moments(t1, t2);
     const u128 q2 = (u128)t2 + (u128)(2ull * rmin) * t1 + (u128)((uint64_t)rmin * rmin) * N;
     s1 = (uint64_t)t1 + (uint64_t)rmin * N;
     s2 = (uint64_t)q2;
