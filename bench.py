@@ -237,15 +237,17 @@ def segment_leg(args, ctx, batch, samples, desc, prm, stream) -> dict:
     }
 
 
-def stats_leg(args, batch, samples, desc, prm, ctx, stream) -> dict:
-    """Per-row latency statistics (ks_stats_batch) of the whole batch: one read of the samples."""
+def stats_leg(args, batch, samples, desc, prm, ctx, stream, out=None) -> dict:
+    """Per-row latency statistics (ks_stats_batch) of the whole batch: one read of the samples.
+    `out` is an output buffer of at least 32 bytes per row allocated beforehand, or None."""
     import numpy as np
     import torch
 
     import paper_2511_05958_amd as P
 
     rows = int(batch.specs["K"].astype(np.int64).sum())
-    out = torch.empty(rows * 32, dtype=torch.uint8, device="cuda")
+    if out is None or out.numel() < rows * 32:
+        out = torch.empty(rows * 32, dtype=torch.uint8, device="cuda")
 
     def step():
         P.ks_stats_batch(ctx.handle, samples, desc, batch.num_series, prm.max_K, out, stream=stream)
@@ -449,6 +451,30 @@ def read_ceiling(args) -> int:
     return 0
 
 
+def reserve_outputs(args, ctx, keys):
+    """Allocate the per-row buffers of the learned and statistics legs before any sample batch, as an
+    application sizes its workspaces before loading data: the learned-path workspace for every workload
+    in `keys` whose learned leg runs, and the statistics output of the first one (None if skipped)."""
+    import numpy as np
+    import torch
+
+    import paper_2511_05958_amd as P
+    from paper_2511_05958_amd import synth as S
+
+    stats_out = None
+    for i, key in enumerate(keys):
+        recipe, count, _ = WORKLOADS[key]
+        spec = S.make_batch(recipe, num_series=count).specs
+        if spec["N"].max() > P.KS_FEATURE_MAX_N:
+            continue
+        mp = args.model if (i == 0 and args.model) else os.path.join(MODEL_DIR, MODELS.get(key, "proposal_r4.ckpt"))
+        if not args.no_learned and os.path.exists(mp):
+            P.ks_learn_reserve(ctx.handle, len(spec), int(spec["K"].max()))
+        if i == 0 and not args.no_stats:
+            stats_out = torch.empty(int(spec["K"].astype(np.int64).sum()) * 32, dtype=torch.uint8, device="cuda")
+    return stats_out
+
+
 def plain_scan(args, ctx, key, stream, launch="autotune"):
     """Generate workload `key` in HBM and time the plain exact scan on it: (record, state)."""
     import numpy as np
@@ -581,6 +607,7 @@ def main() -> int:
     model_path = args.model or os.path.join(MODEL_DIR, MODELS.get(args.workload, "proposal_r4.ckpt"))
     ctx = P.Context(0)
     stream = torch.cuda.current_stream()
+    stats_buf = reserve_outputs(args, ctx, [args.workload] + extras)
     rec, (batch, samples, desc, out, prm, res) = plain_scan(args, ctx, args.workload, stream, args.launch)
     n = batch.num_series
     line = {
@@ -612,11 +639,12 @@ def main() -> int:
     if not args.no_segment:
         line["segment"] = segment_leg(args, ctx, batch, samples, desc, prm, stream)
     if not args.no_stats and batch.specs["N"].max() <= P.KS_FEATURE_MAX_N:
-        line["row_stats"], stats_out = stats_leg(args, batch, samples, desc, prm, ctx, stream)
+        line["row_stats"], stats_out = stats_leg(args, batch, samples, desc, prm, ctx, stream, stats_buf)
         if not args.no_check:
             line["check"] = check_leg(args, ctx, batch, desc, prm, out, stats_out, line["row_stats"]["ms_per_step"],
                                       stream)
         del stats_out
+    stats_buf = None
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(batch, samples)
     del samples, desc, out

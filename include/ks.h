@@ -287,6 +287,17 @@ int ks_model_grads(ks_model *model, float *grads);
 int ks_model_save(ks_model *model, const char *path);
 int ks_model_load(ks_model *model, const char *path);
 
+/* Pre-allocate the learned-path workspace (per-row moments, features,
+ * activations, logits; the training buffers too when `train` is nonzero) for
+ * batches of up to max_series series with K <= max_K (0 = KS_MAX_K), so that
+ * ks_features, ks_propose, ks_refine and the network calls of that size
+ * allocate nothing. Optional: those calls grow the workspace on demand, but a
+ * caller that reserves before loading its samples also keeps the per-row
+ * buffers apart from the sample allocation. KS_E_RANGE for max_K outside
+ * [2, KS_MAX_K] or max_series above 2^26, KS_E_NOMEM when the device is full
+ * (the workspace is then empty). Synchronises the device when it grows. */
+int ks_learn_reserve(ks_ctx *ctx, uint32_t max_series, uint32_t max_K, int train);
+
 /* Feature pass: per-row moments kept in the context (for ks_refine) and
  * decile features, written to `features` (device, nullable, float[rows][9],
  * series s at rows aux_offset .. aux_offset + K - 1 when they fit in

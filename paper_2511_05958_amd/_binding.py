@@ -108,6 +108,7 @@ _SIGNATURES = {
     "ks_ctx_create": ([ctypes.c_int, _vp], ctypes.c_int),
     "ks_ctx_destroy": ([_vp], ctypes.c_int),
     "ks_reserve": ([_vp, _u32, _u64], ctypes.c_int),
+    "ks_learn_reserve": ([_vp, _u32, _u32, ctypes.c_int], ctypes.c_int),
     "ks_scan_batch": ([_vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp, _u64, _vp], ctypes.c_int),
     "ks_launch_set": ([_vp, _u32, _u32, _vp], ctypes.c_int),
     "ks_launch_get": ([_vp, _u32, _u32, _vp], ctypes.c_int),
@@ -214,6 +215,10 @@ def ks_ctx_destroy(ctx) -> None:
 
 def ks_reserve(ctx, max_series: int, max_total_steps: int) -> None:
     _check(lib().ks_reserve(ctx, max_series, max_total_steps), "ks_reserve")
+
+
+def ks_learn_reserve(ctx, max_series: int, max_K: int = 0, train: bool = False) -> None:
+    _check(lib().ks_learn_reserve(ctx, max_series, max_K, 1 if train else 0), "ks_learn_reserve")
 
 
 def ks_scan_batch(ctx, samples, desc, num_series: int, params: ks_params, out, all_U=None, stream=None,

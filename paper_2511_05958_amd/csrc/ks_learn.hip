@@ -333,6 +333,17 @@ int ks_model_load(ks_model* m, const char* path) {
   return KS_OK;
 }
 
+int ks_learn_reserve(ks_ctx* ctx, uint32_t max_series, uint32_t max_K, int train) {
+  if (!ctx) return KS_E_INVALID;
+  if (max_K == 0) max_K = KS_MAX_K;
+  if (int rc = check_learn_args(nullptr, 0, max_K)) return rc;
+  if (max_series > (1u << 26)) return KS_E_RANGE;
+  if (max_series == 0) return KS_OK;
+  DeviceGuard g(ctx->device);
+  if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+  return ensure_learn(ctx, (uint64_t)max_series * slot_rows(max_K), max_series, train != 0);
+}
+
 int ks_features(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, const ks_desc* desc,
                 uint32_t num_series, uint32_t max_K, float* features, uint64_t feature_rows, void* stream) {
   if (!ctx) return KS_E_INVALID;

@@ -54,3 +54,4 @@ def test_null_arguments_rejected_without_device():
     assert lib.ks_ctx_destroy(None) == P.KS_E_INVALID
     assert lib.ks_ctx_create(0, None) == P.KS_E_INVALID
     assert lib.ks_reserve(None, 1, 1) == P.KS_E_INVALID
+    assert lib.ks_learn_reserve(None, 1, 16, 0) == P.KS_E_INVALID

@@ -61,6 +61,32 @@ def test_features_bit_exact(ctx, recipe, num):
         assert np.array_equal(f[a:a + len(ref)], ref), t
 
 
+def test_learn_reserve_then_features():
+    """A reserved workspace (fresh context, reserved before any learned call, then a smaller and a
+    training reservation) serves the feature pass, which stays bit-exact; bad sizes are rejected."""
+    b, x, d = gen(3, 12)
+    c = P.Context(0)
+    try:
+        for mk, n in [(1, 4), (P.KS_MAX_K + 1, 4)]:
+            with pytest.raises(P.KsError) as e:
+                P.ks_learn_reserve(c.handle, n, mk)
+            assert e.value.code == P.KS_E_RANGE
+        with pytest.raises(P.KsError) as e:
+            P.ks_learn_reserve(c.handle, (1 << 26) + 1, 64)
+        assert e.value.code == P.KS_E_RANGE
+        P.ks_learn_reserve(c.handle, 0, 64)
+        P.ks_learn_reserve(c.handle, len(d), int(d["K"].max()))
+        P.ks_learn_reserve(c.handle, 2, 32)
+        P.ks_learn_reserve(c.handle, len(d), int(d["K"].max()), train=True)
+        f = gpu_features(c, x, d, int(d["K"].max()))
+    finally:
+        c.close()
+    for t in range(len(d)):
+        a = int(d[t]["aux_offset"])
+        ref = O.features(series(x, d, t))
+        assert np.array_equal(f[a:a + len(ref)], ref), t
+
+
 def test_features_edge_cases(ctx):
     rng = np.random.default_rng(3)
     ss = [np.full((5, 1), 7, np.uint32), np.full((3, 40), 9, np.uint32),
