@@ -41,6 +41,9 @@ constexpr uint32_t kSegDepths = KS_MAX_K + 1;  // counter pairs: a window of a l
 // Depth 0: the full scan of series blockIdx.x (as scan_kernel, in workgroups
 // of kSegRootNT threads: the streaming depth is HBM-bound like the plain
 // scan), also storing each row's moments and minimum at rows[s * row_stride + i].
+// The rows' minima wait in the key buffer (free until the keys are made) and
+// the records are written once the series is streamed, consecutive threads
+// taking consecutive rows, rather than one 24-byte store per row as it ends.
 constexpr int kSegRootNT = 512;
 
 template <int KMAX>
@@ -66,10 +69,13 @@ __global__ __launch_bounds__(kSegRootNT) void seg_root_kernel(const uint32_t* __
                                                 sm.u.mom.s1[i] = s1;
                                                 sm.u.mom.s2lo[i] = s2;
                                                 sm.u.mom.s2hi[i] = s2h;
-                                                rm[i] = ks::RowMom{s1, s2, s2h, rmin};
+                                                sm.key[0][i] = rmin;
                                               }
                                             });
-  const uint32_t gmin = ks::block_min_u32<kSegRootNT>(mn, sm.red);
+  const uint32_t gmin = ks::block_min_u32<kSegRootNT>(mn, sm.red);  // its barriers publish the rows
+  for (uint32_t i = threadIdx.x; i < d.K; i += kSegRootNT)
+    rm[i] = ks::RowMom{sm.u.mom.s1[i], sm.u.mom.s2lo[i], sm.u.mom.s2hi[i], sm.key[0][i]};
+  __syncthreads();  // the minima are read before the keys overwrite them
   ks::finish_series(sm, d.K, d.N, gmin, prm, out + s, nullptr);
 }
 
