@@ -88,13 +88,13 @@ struct FeatStage {
 // the deciles (as raw samples, at row slot s * SR + 2 + i of feat_ws) and the
 // refine workspace's moments, and per series its minimum and K.
 template <int NB, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 : 1))) void features_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_per_eu(NB)))) void features_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                       const ks_desc* __restrict__ desc, uint32_t num_series,
                                                       uint32_t max_K, uint32_t SR, LearnWs lw,
                                                       float* __restrict__ feat_ws,
                                                       const uint32_t* __restrict__ plan) {
   constexpr int W = NT / kWave;
-  __shared__ SelLds sel[W];
+  __shared__ RowLds sel[W];
   __shared__ FeatStage stage[W];
   __shared__ uint32_t red[W];
   const uint32_t ci = feat_class_index(NB);
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NB == 4 ? 3 
   }
   const uint32_t K = d.K, N = d.N;
   const uint64_t slot = (uint64_t)s * SR + 2;
-  SelLds& L = sel[w];
+  RowLds& L = sel[w];
   FeatStage& st = stage[w];
   const uint32_t B = (K + W - 1) / W;
   const uint32_t begin = min(w * B, K), end = min(begin + B, K);

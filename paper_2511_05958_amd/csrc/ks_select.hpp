@@ -27,8 +27,8 @@ namespace ks {
 // Radix levels, for targets that fall into the last bin (and for rows whose
 // range needs all 32 bits): an MSD radix select over the keys of that bin.
 // Level 0 histograms the top kSelW0 bits of every key; each later level
-// histograms the next kSelW bits of only the keys that share a target's prefix
-// so far. Those keys form at most nine groups (one per distinct prefix among
+// histograms the next kSelW bits (kSelWs in stream_select) of only the keys
+// that share a target's prefix so far. Those keys form at most nine groups (one per distinct prefix among
 // the targets), numbered in target order; histograms are LDS counters per
 // (group, digit) bin. Two forms:
 //   radix_select  keeps the keys in registers (the key arrays of the workflow
@@ -52,6 +52,16 @@ struct __align__(16) SelLds {
   uint32_t hist[(kSelNone + 1) << kSelW];  // bin counts, then exclusive prefixes
   uint8_t tab[(kSelNone + 1) << kSelW];    // bin -> group at the next level
 };
+
+// The row pass's share of LDS per wave: the window, which stream_select's
+// levels reuse (later digits of kSelWs bits, so that nine groups' bins fit),
+// and the groups' prefixes. 4.2 KiB, so that eight waves per SIMD fit.
+constexpr uint32_t kSelWs = 6;
+struct __align__(16) RowLds {
+  uint32_t hist[kSelWin];
+  uint32_t gp[16];
+};
+static_assert((kSelNone << kSelWs) <= kSelWin && (1u << kSelW0) <= kSelWin, "stream_select's bins fit the window");
 static_assert((1u << kSelW0) <= ((kSelNone + 1) << kSelW), "level-0 bins fit the histogram");
 static_assert(kSelWin == 16u * kWave && kSelWin + kWave <= ((kSelNone + 1) << kSelW),
               "16 window bins per lane and a spare word per lane fit");
@@ -193,8 +203,8 @@ __device__ __forceinline__ uint32_t radix_select(SelLds& L, uint32_t (&k)[V], ui
 // N keys in all). Lane j < RANKS::kCount gets the bin of the key of rank
 // RANKS::rank(j, N); a target whose bin is the last one gets last = true and
 // r, its rank among the keys of that bin.
-template <class RANKS>
-__device__ __forceinline__ uint32_t window_find(SelLds& L, uint32_t N, uint32_t lane, uint32_t& r, bool& last) {
+template <class RANKS, class LDS>
+__device__ __forceinline__ uint32_t window_find(LDS& L, uint32_t N, uint32_t lane, uint32_t& r, bool& last) {
   static_assert(RANKS::kCount >= 1 && RANKS::kCount <= kSelNone, "at most nine targets");
   const bool tl = lane < RANKS::kCount;
   wave_lds_sync();
@@ -417,7 +427,7 @@ struct RowScan {
 // not read after this returns, so the caller may load the next row into it
 // while row_select runs.
 template <int NB>
-__device__ __forceinline__ RowScan row_scan(SelLds& L, const Batch (&B)[NB], const RowGeo& g, uint32_t N,
+__device__ __forceinline__ RowScan row_scan(RowLds& L, const Batch (&B)[NB], const RowGeo& g, uint32_t N,
                                             uint64_t& s1, uint64_t& s2, uint32_t& s2h, uint32_t lane) {
   // clear the window now: the LDS writes overlap the minimum / maximum pass
   u32x4* hv = reinterpret_cast<u32x4*>(L.hist);
@@ -504,10 +514,10 @@ __device__ __forceinline__ RowScan row_scan(SelLds& L, const Batch (&B)[NB], con
 // or more. The key's group at a level is the index of its prefix among the
 // groups' prefixes (kept in LDS), compared one by one. Counts are full 32-bit
 // (rows of any length).
-__device__ __forceinline__ uint32_t stream_select(SelLds& L, const uint32_t* __restrict__ samples, const RowGeo& g,
+__device__ __forceinline__ uint32_t stream_select(RowLds& L, const uint32_t* __restrict__ samples, const RowGeo& g,
                                                uint32_t rmin, uint32_t off, uint32_t bits, uint32_t R, bool tl,
                                                uint32_t lane) {
-  uint32_t* gp = reinterpret_cast<uint32_t*>(L.tab);  // prefixes of the groups, in target order
+  uint32_t* gp = L.gp;  // prefixes of the groups, in target order
   const uint64_t tm = ballot(tl);
   const uint32_t first = tm ? (uint32_t)__builtin_ctzll(tm) : 0u;
   uint32_t tg = 0, key = 0, G = 1, sprev = bits, wmax = kSelW0;
@@ -576,7 +586,7 @@ __device__ __forceinline__ uint32_t stream_select(SelLds& L, const uint32_t* __r
     tg = id;
     G = (uint32_t)__popcll(m);
     sprev = s;
-    wmax = kSelW;
+    wmax = kSelWs;
     level0 = false;
   }
   return key;
@@ -585,7 +595,7 @@ __device__ __forceinline__ uint32_t stream_select(SelLds& L, const uint32_t* __r
 // One row, second part (after row_scan): lane j < RANKS::kCount returns the
 // sample of rank RANKS::rank(j, N) in the row.
 template <int NB, class RANKS>
-__device__ __forceinline__ uint32_t row_select(SelLds& L, const uint32_t* __restrict__ samples, const RowGeo& g,
+__device__ __forceinline__ uint32_t row_select(RowLds& L, const uint32_t* __restrict__ samples, const RowGeo& g,
                                                const RowScan& rs, uint32_t N, uint32_t lane) {
   if (rs.b == 0) return rs.rmin;
   uint32_t key = 0, r, off, bits;
@@ -650,7 +660,7 @@ struct RowOut {
 // Lane j < RANKS::kCount: the sample of rank RANKS::rank(j, N), from the
 // window histogram in L of the keys r - base (every sample >= base).
 template <class RANKS>
-__device__ __forceinline__ uint32_t select_from_window(SelLds& L, const uint32_t* __restrict__ samples,
+__device__ __forceinline__ uint32_t select_from_window(RowLds& L, const uint32_t* __restrict__ samples,
                                                        const RowGeo& g, uint32_t base, uint32_t rmax, uint32_t N,
                                                        uint32_t lane) {
   uint32_t r;
@@ -670,7 +680,7 @@ __device__ __forceinline__ uint32_t select_from_window(SelLds& L, const uint32_t
 // into a fresh window (unless the range needs all 32 bits), and the order
 // statistics selected.
 template <class RANKS>
-__device__ __forceinline__ void row_exact(SelLds& L, const uint32_t* __restrict__ samples, const RowGeo& g,
+__device__ __forceinline__ void row_exact(RowLds& L, const uint32_t* __restrict__ samples, const RowGeo& g,
                                           uint32_t N, uint32_t lane, RowOut& o) {
   const uint32_t rmin = o.rmin;
   const uint32_t range = o.rmax - rmin;
@@ -722,7 +732,7 @@ __device__ __forceinline__ void row_exact(SelLds& L, const uint32_t* __restrict_
 constexpr uint32_t kSelMargin = 128;
 
 template <class RANKS, class Emit>
-__device__ __forceinline__ void select_rows_long(SelLds& L, const uint32_t* __restrict__ samples, uint64_t off0,
+__device__ __forceinline__ void select_rows_long(RowLds& L, const uint32_t* __restrict__ samples, uint64_t off0,
                                                  uint32_t N, uint32_t K, uint32_t first, uint32_t step, uint32_t lane,
                                                  Emit&& emit) {
   struct Cursor {
@@ -825,6 +835,14 @@ __device__ __forceinline__ void select_rows_long(SelLds& L, const uint32_t* __re
 // them are held in registers (class 1, 2, 4), longer rows are streamed
 // (class kStreamed).
 constexpr uint32_t kStreamed = 8;
+// Waves per SIMD the row-pass kernels are compiled for, by row class (1 = the
+// compiler's choice). With 4.3 KiB of LDS per wave the register file sets the
+// occupancy; these are the largest targets met without spills (feature pass:
+// 6 at 80 registers; statistics pass: 7 at 72), which run rows of up to 1027
+// samples 6% and 9% faster than the 5 waves the compiler picks by itself.
+// Rows of 2048 samples keep the compiler's 4 (5 spills and runs slower).
+__host__ __device__ constexpr int feat_waves_per_eu(int NB) { return NB == 1 ? 6 : NB == 4 ? 3 : 1; }
+__host__ __device__ constexpr int stats_waves_per_eu(int NB) { return NB == 1 ? 7 : 1; }
 __host__ __device__ constexpr uint32_t feat_batches(uint32_t N) {
   return (N / 4 + 4u * kWave - 1) / (4u * kWave) <= 1
              ? 1u

@@ -42,13 +42,13 @@ __device__ double u128_to_double(u128 v) {
 }
 
 template <int NB>
-__global__ __launch_bounds__(256) void row_stats_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_waves_per_eu(NB)))) void row_stats_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                         const ks_desc* __restrict__ desc, uint32_t num_series,
                                                         uint32_t max_K, ks_row_stats* __restrict__ out,
                                                         uint64_t out_rows) {
   constexpr int W = 4;
   constexpr uint32_t kStage = 16;  // rows per contiguous write of a wave's records
-  __shared__ ks::SelLds sel[W];
+  __shared__ ks::RowLds sel[W];
   __shared__ __align__(16) uint32_t stage[W][kStage * 8];
   const uint32_t s = blockIdx.x;
   if (s >= num_series) return;
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void row_stats_kernel(const uint32_t* __restri
     return;
   }
   const uint32_t K = d.K, N = d.N;
-  ks::SelLds& L = sel[w];
+  ks::RowLds& L = sel[w];
   // wave w takes rows [w B, (w + 1) B) and writes every kStage rows' records as
   // contiguous 16-byte stores (records written one at a time, by waves
   // interleaved row by row, left partly written cache lines behind)
