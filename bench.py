@@ -451,6 +451,44 @@ def read_ceiling(args) -> int:
     return 0
 
 
+def row_length_sweep(args) -> int:
+    """Feature pass (ks_features) and statistics pass (ks_stats_batch) against row length: 4 GiB of
+    samples per length, 256 rows per series, values uniform on [200, 500) (every decile inside the
+    1024-bin window, as in latency rows). Shows the fixed per-row cost of the row pass."""
+    import numpy as np
+    import torch
+
+    import paper_2511_05958_amd as P
+
+    ctx = P.Context(0)
+    st = torch.cuda.current_stream()
+    points = []
+    K = 256
+    for N in (64, 128, 256, 512, 1024, 2048):
+        n = (4 << 30) // (K * N * 4)
+        total = n * K * N
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(1000 + N)
+        x = torch.randint(0, 300, (total,), device="cuda", dtype=torch.int32, generator=gen) + 200
+        d = P.make_desc(np.arange(n, dtype=np.uint64) * (K * N), np.full(n, K, np.uint32), np.full(n, N, np.uint32))
+        dd = P.to_device(d)
+        rows = n * K
+        P.ks_learn_reserve(ctx.handle, n, K)
+        out = torch.empty(rows * 32, dtype=torch.uint8, device="cuda")
+        pt = {"N": N, "series": n, "rows": rows, "bytes": total * 4}
+        for name, fn in (("features", lambda: P.ks_features(ctx.handle, x, dd, n, K, None, stream=st)),
+                         ("stats", lambda: P.ks_stats_batch(ctx.handle, x, dd, n, K, out, stream=st))):
+            ms = timed(args, st, fn)
+            pt[name] = {"ms": ms, "ns_per_row": ms * 1e6 / rows, "TBps": total * 4 / ms / 1e9}
+        points.append(pt)
+        print(json.dumps(pt), flush=True)
+        del x, out, dd
+        torch.cuda.empty_cache()
+    ctx.close()
+    print(json.dumps({"workload": "rowlen", "points": points}), flush=True)
+    return 0
+
+
 def reserve_outputs(args, ctx, keys):
     """Allocate the per-row buffers of the learned and statistics legs before any sample batch, as an
     application sizes its workspaces before loading data: the learned-path workspace for every workload
@@ -564,7 +602,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["copy", "ceiling"])
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["copy", "ceiling", "rowlen"])
     ap.add_argument("--extra", default="c2,c3",
                     help="comma-separated workloads whose plain scan and learned leg are added under 'workloads' "
                          "('' for none)")
@@ -600,6 +638,8 @@ def main() -> int:
         return copy_calibration(args)
     if args.workload == "ceiling":
         return read_ceiling(args)
+    if args.workload == "rowlen":
+        return row_length_sweep(args)
     extras = [w for w in args.extra.split(",") if w and w != args.workload]
     for w in extras:
         if w not in WORKLOADS:

@@ -135,18 +135,19 @@ __global__ __launch_bounds__(NTC) void conv_kernel(const uint16_t* __restrict__ 
 }
 
 // ------------------------------------------------------------ fused forward
-// The whole network over tiles of FT rows, for inference. A tile's frame is
-// its FT rows plus FH = 8 halo rows on each side (2 per layer): frame row f is
-// sequence row r0 - FH + f. Every layer computes all FR = FT + 16 frame rows
-// (nine 16-row MFMA blocks); the rows within 2l of the frame's ends are wrong
-// after layer l (their inputs fall off the frame) but never reach the rows
-// [FH, FH + FT) whose logits are written. Activations stay in LDS as bf16,
+// The whole network over tiles of FT rows, for inference. Tiles follow the
+// series: tile f of series s starts at its row f FT (slot row s SR + 2 + f FT),
+// for f < ceil(K / FT), so no tile is spent on a slot's padding, and a tile
+// writes the logits of its own series' rows only (the padding's logits are
+// never read). A tile's frame is its FT rows plus FH = 8 halo rows on each
+// side (2 per layer): frame row f is slot row r0 - FH + f. Every layer
+// computes all FR = FT + 16 frame rows (nine 16-row MFMA blocks); the rows
+// within 2l of the frame's ends are wrong after layer l (their inputs fall off
+// the frame) but never reach the rows [FH, FH + FT) whose logits are written. Activations stay in LDS as bf16,
 // zeroed on rows outside their series exactly as the per-layer kernels write
 // them, and each output accumulates over j in the per-layer kernels' order
 // (same MFMA steps, bias added last). Wave w owns output channels 16w .. 16w + 15
 // of layers 0..2 and keeps their weights in registers for the whole launch.
-// A frame with no row inside a series (slot padding after a short series)
-// only writes its zero logits.
 constexpr int FT = 128;
 constexpr int FH = 8;
 constexpr int FR = FT + 2 * FH;  // 144
@@ -226,6 +227,7 @@ __device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ in, int
 // logits [rows] fp32 (0 on rows outside every series).
 __global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(3))) void fused_forward_kernel(const uint16_t* __restrict__ x0, uint64_t rows,
                                                             uint32_t SR, const uint32_t* __restrict__ Ks,
+                                                            uint32_t num_series, uint32_t tiles_per_series,
                                                             const uint16_t* __restrict__ w0,
                                                             const uint16_t* __restrict__ w1,
                                                             const uint16_t* __restrict__ w2,
@@ -256,22 +258,20 @@ __global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(3))) void f
     const uint32_t r = q / FXS, c = q - r * FXS, br = r < 2 ? r : FR + r;
     sm.x[br * FXS + c] = 0;
   }
-  const uint64_t ntiles = (rows + FT - 1) / FT;
+  const uint64_t ntiles = (uint64_t)num_series * tiles_per_series;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t r0 = (int64_t)(tile * FT);
+    const uint32_t ser = (uint32_t)(tile / tiles_per_series);
+    const uint32_t t0 = (uint32_t)(tile - (uint64_t)ser * tiles_per_series) * FT;  // the tile's first row in its series
+    const uint32_t K = Ks[ser];
+    if (t0 >= K) continue;  // past the series' last row (block-uniform)
+    const uint64_t sbase = (uint64_t)ser * SR + 2;
+    const int64_t r0 = (int64_t)(sbase + t0);
     __syncthreads();
     // frame row f = tid (FR <= NTC): its validity as one bit per row, by ballot
     const int64_t vrow = r0 - FH + (int64_t)tid;
     const bool v = tid < (uint32_t)FR && vrow >= 0 && row_valid((uint64_t)vrow, rows, SR, Ks);
     const uint64_t vb = ballot(v);
-    if (lane == 0) sm.valid[w] = vb;
-    if (!__syncthreads_or(v)) {
-      // no row of the frame lies in a series (slot padding past a short
-      // series): every activation is zero there, so every logit is 0
-      for (uint32_t f = tid; f < (uint32_t)FT; f += NTC)
-        if ((uint64_t)r0 + f < rows) logits[(uint64_t)r0 + f] = 0.0f;
-      continue;
-    }
+    if (lane == 0) sm.valid[w] = vb;  // read after the barrier below
     for (uint32_t q = tid; q < 2u * FR; q += NTC) {
       const uint32_t f = q >> 1, h = q & 1u;
       const int64_t row = r0 - FH + (int64_t)f;
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(3))) void f
         for (int e = 0; e < 4; ++e) {
           const int f = blk * 16 + (int)kg * 4 + e;
           const int64_t row = r0 - FH + f;
-          if (f >= FH && f < FH + FT && (uint64_t)row < rows) logits[row] = ((lrows >> (4 * blk + e)) & 1u) ? acc[e] + bias3 : 0.0f;
+          if (f >= FH && f < FH + FT && (uint64_t)row - sbase < K) logits[row] = acc[e] + bias3;
         }
       }
     }

@@ -103,11 +103,13 @@ hipError_t forward(ks_ctx* c, const ks_model* m, uint64_t rows, uint32_t SR, hip
 // Inference: the whole network in one launch, activations kept in LDS.
 hipError_t forward_infer(ks_ctx* c, const ks_model* m, uint64_t rows, uint32_t SR, hipStream_t st) {
   LearnBuffers& b = c->learn;
-  const uint64_t tiles = (rows + C::FT - 1) / C::FT;
+  const uint32_t num_series = (uint32_t)(rows / SR);
+  const uint32_t per = (SR - 4 + C::FT - 1) / C::FT;  // tiles covering a slot's K <= SR - 4 rows
+  const uint64_t tiles = (uint64_t)num_series * per;
   const uint64_t cap = (uint64_t)c->num_cus * 3;  // three 51 KB workgroups per CU
   const uint32_t g = (uint32_t)(tiles < cap ? (tiles ? tiles : 1) : cap);
-  hipLaunchKernelGGL(C::fused_forward_kernel, dim3(g), dim3(C::NTC), 0, st, b.x0, rows, SR, b.K, m->wf[0], m->wf[1],
-                     m->wf[2], m->wf[3], m->b[0], m->b[1], m->b[2], m->b[3], b.logits);
+  hipLaunchKernelGGL(C::fused_forward_kernel, dim3(g), dim3(C::NTC), 0, st, b.x0, rows, SR, b.K, num_series, per,
+                     m->wf[0], m->wf[1], m->wf[2], m->wf[3], m->b[0], m->b[1], m->b[2], m->b[3], b.logits);
   return hipGetLastError();
 }
 
