@@ -172,8 +172,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
 // buffer, element by element (consecutive threads, consecutive elements);
 // then the chunk's network input rows (bf16 of the nine features and the two
 // position channels, channels 11..15 zero), staged in LDS, are written as
-// 16-byte stores. Slot rows outside [2, 2 + K) (the convolutions' zero
-// padding) and every row of a malformed series (K = 0) are zero.
+// 16-byte stores. The two slot rows on each side of [2, 2 + K) (the
+// convolutions' zero padding) and the first four rows of a malformed series
+// (K = 0) are zero; a chunk wholly past row K + 4 writes nothing, as no
+// output row of the network reads its inputs there.
 template <int NT>
 __global__ __launch_bounds__(NT) void feature_pack_kernel(const ks_desc* __restrict__ desc, uint32_t num_series,
                                                           float* __restrict__ feat_out, uint64_t feat_rows,
@@ -187,6 +189,7 @@ __global__ __launch_bounds__(NT) void feature_pack_kernel(const ks_desc* __restr
   if (r0 >= SR) return;
   const uint32_t nr = SR - r0 < (uint32_t)NT ? SR - r0 : (uint32_t)NT;
   const uint32_t K = lw.K[s];
+  if (r0 >= K + 4u) return;
   const uint64_t row0 = (uint64_t)s * SR + r0;
   // rows [lo, hi) of the chunk hold data
   const uint32_t lo = r0 < 2u ? 2u - r0 : 0u;
