@@ -130,11 +130,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
       wave_lds_sync();
       const uint64_t r0 = slot + i - j;
       for (uint32_t q = lane; q < (j + 1) * 9; q += kWave)
-        __builtin_nontemporal_store(__uint_as_float(st.dec[q]), &feat_ws[r0 * 9 + q]);
+        row_out_store<NB>(__uint_as_float(st.dec[q]), &feat_ws[r0 * 9 + q]);
       if (lane <= j) {
-        __builtin_nontemporal_store(st.s1[lane], &lw.s1[r0 + lane]);
-        __builtin_nontemporal_store(st.s2lo[lane], &lw.s2lo[r0 + lane]);
-        __builtin_nontemporal_store(st.s2hi[lane], &lw.s2hi[r0 + lane]);
+        row_out_store<NB>(st.s1[lane], &lw.s1[r0 + lane]);
+        row_out_store<NB>(st.s2lo[lane], &lw.s2lo[r0 + lane]);
+        row_out_store<NB>(st.s2hi[lane], &lw.s2hi[r0 + lane]);
       }
       wave_lds_sync();
     }

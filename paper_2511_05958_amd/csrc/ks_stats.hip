@@ -84,8 +84,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_w
     if (j + 1 == kStage || i + 1 == end) {  // flush rows i - j .. i
       ks::wave_lds_sync();
       if (lane < 2 * (j + 1))
-        __builtin_nontemporal_store(reinterpret_cast<const ks::u32x4*>(st)[lane],
-                                    &reinterpret_cast<ks::u32x4*>(o + (i - j))[lane]);
+        ks::row_out_store<NB>(reinterpret_cast<const ks::u32x4*>(st)[lane],
+                              &reinterpret_cast<ks::u32x4*>(o + (i - j))[lane]);
       ks::wave_lds_sync();
     }
   };
