@@ -23,25 +23,26 @@ struct LearnWs {
 };
 
 // Series order of the feature pass (one workgroup): per row class (1, 2 or 4
-// load batches, or streamed) the series largest first, bucketed by the bit
+// load batches, streamed, or short rows four to a wave) the series largest first, bucketed by the bit
 // length of their sample bytes (a longest-processing-time order, so a
 // class's launch starts its longest workgroups first and no workgroup waits
 // behind a class it does not belong to); malformed series last in class 1.
 // plan[0 .. n) is the order, plan[n + c] the first index of class c and
-// plan[n + 4 + c] its count.
+// plan[n + kFeatClasses + c] its count.
 constexpr int kFeatPlanNT = 1024;
 constexpr uint32_t kFeatBuckets = 40;
 
+constexpr uint32_t kFeatClasses = 5;
 __device__ __forceinline__ uint32_t feat_class_index(uint32_t NB) {
-  return NB == 1 ? 0u : (NB == 2 ? 1u : (NB == 4 ? 2u : 3u));
+  return NB == 1 ? 0u : (NB == 2 ? 1u : (NB == 4 ? 2u : (NB == kStreamed ? 3u : 4u)));
 }
 
 __global__ __launch_bounds__(kFeatPlanNT) void feature_plan_kernel(const ks_desc* __restrict__ desc,
                                                                    uint32_t num_series, uint64_t num_samples,
                                                                    uint32_t max_K, uint32_t* __restrict__ plan) {
-  __shared__ uint32_t cnt[4 * kFeatBuckets];
+  __shared__ uint32_t cnt[kFeatClasses * kFeatBuckets];
   const uint32_t tid = threadIdx.x;
-  for (uint32_t i = tid; i < 4 * kFeatBuckets; i += kFeatPlanNT) cnt[i] = 0;
+  for (uint32_t i = tid; i < kFeatClasses * kFeatBuckets; i += kFeatPlanNT) cnt[i] = 0;
   __syncthreads();
   auto key = [&](uint32_t s) -> uint32_t {
     const ks_desc d = desc[s];
@@ -54,14 +55,14 @@ __global__ __launch_bounds__(kFeatPlanNT) void feature_plan_kernel(const ks_desc
   __syncthreads();
   if (tid == 0) {
     uint32_t run = 0;
-    for (uint32_t c = 0; c < 4; ++c) {
+    for (uint32_t c = 0; c < kFeatClasses; ++c) {
       plan[num_series + c] = run;
       for (uint32_t b = 0; b < kFeatBuckets; ++b) {
         const uint32_t k = cnt[c * kFeatBuckets + b];
         cnt[c * kFeatBuckets + b] = run;
         run += k;
       }
-      plan[num_series + 4 + c] = run - plan[num_series + c];
+      plan[num_series + kFeatClasses + c] = run - plan[num_series + c];
     }
   }
   __syncthreads();
@@ -81,10 +82,10 @@ struct FeatStage {
 };
 
 // First step, workgroup t of the launch of row class NB (rows in 1, 2 or 4
-// load batches held in registers, or kStreamed) takes the t-th series of that
-// class in the plan's order (the NB = 1 launch also marks malformed series
-// with K = 0). One wave per row; wave w takes rows [w B, (w + 1) B) with
-// B = ceil(K / 4). Writes per row
+// load batches held in registers, kStreamed, or kGrouped) takes the t-th
+// series of that class in the plan's order (the NB = 1 launch also marks
+// malformed series with K = 0). One wave per row (four per step for kGrouped);
+// wave w takes rows [w B, (w + 1) B) with B = ceil(K / 4). Writes per row
 // the deciles (as raw samples, at row slot s * SR + 2 + i of feat_ws) and the
 // refine workspace's moments, and per series its minimum and K.
 template <int NB, int NT>
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
   __shared__ FeatStage stage[W];
   __shared__ uint32_t red[W];
   const uint32_t ci = feat_class_index(NB);
-  if (blockIdx.x >= plan[num_series + 4 + ci]) return;
+  if (blockIdx.x >= plan[num_series + kFeatClasses + ci]) return;
   const uint32_t s = plan[plan[num_series + ci] + blockIdx.x];
   const ks_desc d = desc[s];
   const uint32_t tid = threadIdx.x, lane = lane_id();
@@ -116,7 +117,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
   const uint32_t B = (K + W - 1) / W;
   const uint32_t begin = min(w * B, K), end = min(begin + B, K);
   uint32_t gmin = 0xffffffffu;
-  auto emit = [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t rmin, uint32_t dec) {
+  // row i's results; its deciles on lanes first .. first + 8
+  auto emit = [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t rmin, uint32_t dec, uint32_t first) {
     const uint32_t j = (i - begin) % kFeatStage;
     if (lane == 0) {
       st.s1[j] = s1;
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
     }
     gmin = min(gmin, rmin);
     // feature numerators x - m need the series minimum: keep x itself
-    if (lane < 9) st.dec[j * 9 + lane] = dec;
+    if (lane - first < 9u) st.dec[j * 9 + lane - first] = dec;
     if (j + 1 == kFeatStage || i + 1 == end) {  // flush rows i - j .. i
       wave_lds_sync();
       const uint64_t r0 = slot + i - j;
@@ -141,7 +143,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
   };
   if constexpr (NB == (int)kStreamed) {
     select_rows_long<DecileRanks>(L, samples, d.offset, N, end, begin, 1u, lane,
-                                  [&](uint32_t i, const RowOut& o) { emit(i, o.s1, o.s2, o.s2h, o.rmin, o.sel); });
+                                  [&](uint32_t i, const RowOut& o) { emit(i, o.s1, o.s2, o.s2h, o.rmin, o.sel, 0u); });
+  } else if constexpr (NB == (int)kGrouped) {
+    select_rows_grouped<DecileRanks>(L, samples, d.offset, N, begin, end, lane,
+                                     [&](uint32_t i, const RowOut& o, uint32_t first) {
+                                       emit(i, o.s1, o.s2, o.s2h, o.rmin, o.sel, first);
+                                     });
   } else {
     Batch cur[NB];
     RowGeo g;
@@ -153,7 +160,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
       // the next row's loads are in flight while this row's order statistics are found
       const RowGeo gi = g;
       if (i + 1 < end) g = load_row<NB>(cur, samples, d.offset + (uint64_t)(i + 1) * N, N, lane);
-      emit(i, s1, s2, s2h, rs.rmin, row_select<NB, DecileRanks>(L, samples, gi, rs, N, lane));
+      emit(i, s1, s2, s2h, rs.rmin, row_select<NB, DecileRanks>(L, samples, gi, rs, N, lane), 0u);
     }
   }
   if (lane == 0) red[w] = gmin;

@@ -359,10 +359,11 @@ int ks_features(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
   if (int rc = ensure_learn(ctx, (uint64_t)num_series * SR, num_series, false)) return rc;
   hipStream_t st = (hipStream_t)stream;
   LearnBuffers& b = ctx->learn;
-  // the series order per row class, kept in the logits buffer (num_series + 8
+  // the series order per row class, kept in the logits buffer (num_series + 10
   // words <= its rows; nothing reads the logits before the forward rewrites
-  // them), then one launch per row class (1, 2 or 4 load batches per row, or
-  // streamed): its workgroups past the class's count return at once
+  // them), then one launch per row class (1, 2 or 4 load batches per row,
+  // streamed, or short rows four to a wave): its workgroups past the class's
+  // count return at once
   uint32_t* plan = reinterpret_cast<uint32_t*>(b.logits);
   hipLaunchKernelGGL(ks::feature_plan_kernel, dim3(1), dim3(ks::kFeatPlanNT), 0, st, desc, num_series, num_samples,
                      max_K, plan);
@@ -373,6 +374,8 @@ int ks_features(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
   hipLaunchKernelGGL((ks::features_kernel<4, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
                      num_series, max_K, SR, learn_ws(ctx), b.feat, plan);
   hipLaunchKernelGGL((ks::features_kernel<ks::kStreamed, kNT>), dim3(num_series), dim3(kNT), 0, st, samples,
+                     num_samples, desc, num_series, max_K, SR, learn_ws(ctx), b.feat, plan);
+  hipLaunchKernelGGL((ks::features_kernel<ks::kGrouped, kNT>), dim3(num_series), dim3(kNT), 0, st, samples,
                      num_samples, desc, num_series, max_K, SR, learn_ws(ctx), b.feat, plan);
   hipLaunchKernelGGL((ks::feature_pack_kernel<kNT>), dim3(num_series, (SR + kNT - 1) / kNT), dim3(kNT), 0, st, desc,
                      num_series, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);

@@ -48,6 +48,12 @@ constexpr uint32_t kSelW = 7;      // bits of every later digit
 constexpr uint32_t kSelNone = 9;   // group of keys outside every target's prefix
 constexpr uint32_t kSelEmpty = 0xffffffffu;  // key of a slot without a sample
 
+// Row classes of the row passes (feat_batches): 1, 2, 4 load batches per row
+// held in registers, kStreamed rows read in batches, kGrouped short rows four
+// to a wave.
+constexpr uint32_t kStreamed = 8;
+constexpr uint32_t kGrouped = 16;
+
 struct __align__(16) SelLds {
   uint32_t hist[(kSelNone + 1) << kSelW];  // bin counts, then exclusive prefixes
   uint8_t tab[(kSelNone + 1) << kSelW];    // bin -> group at the next level
@@ -67,13 +73,13 @@ static_assert(kSelWin == 16u * kWave && kSelWin + kWave <= ((kSelNone + 1) << kS
               "16 window bins per lane and a spare word per lane fit");
 static_assert((((kSelNone << kSelW) + 255u) & ~255u) <= ((kSelNone + 1) << kSelW), "padded live bins fit");
 
-// Output store of the row passes: plain for one-batch rows, whose outputs are
+// Output store of the row passes: plain for one-batch and short rows, whose outputs are
 // the larger share of the traffic (the learned step on 4096 x 256 rows of 1024
 // samples ran 1.6% faster than with nontemporal stores), nontemporal for longer
 // rows (plain stores made the 8192 x 1024 x 2048 step 2 - 5% slower).
 template <int NB, typename T>
 __device__ __forceinline__ void row_out_store(T v, T* p) {
-  if constexpr (NB == 1)
+  if constexpr (NB == 1 || NB == (int)kGrouped)
     *p = v;
   else
     __builtin_nontemporal_store(v, p);
@@ -588,7 +594,9 @@ __device__ __forceinline__ uint32_t stream_select(RowLds& L, const uint32_t* __r
     }
     if (s == 0) break;
     // groups of the next level: the targets' distinct bins, in target order
-    const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    // the previous lane's bin, across DPP rows (the targets of a short row
+    // grouped four to a wave may straddle lanes 15 | 16 or 31 | 32)
+    const uint32_t prev = (uint32_t)__shfl((int)x, (int)(lane ? lane - 1u : 0u));
     const bool fresh = tl && (lane == first || x != prev);
     const uint64_t m = ballot(fresh);
     const uint32_t id = mbcnt(m) - (fresh ? 0u : 1u);
@@ -842,21 +850,225 @@ __device__ __forceinline__ void select_rows_long(RowLds& L, const uint32_t* __re
   }
 }
 
-// Row class of the order-statistics kernels: a row of N samples needs
-// ceil(floor(N / 4) / 256) load batches at most; rows of up to 1, 2 or 4 of
-// them are held in registers (class 1, 2, 4), longer rows are streamed
+// ------------------------------------------------- short rows, four to a wave
+// Rows of up to kGroupMaxN samples go four to a wave, one to each 16-lane DPP
+// row (g = lane / 16), loaded like the scan's grouped rows (load_group: up to
+// four quads and one head or tail sample per lane). Their minimum, maximum and
+// moments take four in-row DPP steps, and the four rows share one window: row
+// g counts its keys in byte g of each bin (a row has at most 255 keys, so no
+// byte carries into the next), so one lane-total pass, one wave scan and one
+// pass over the owners' bins serve all four. Row g's targets sit on lanes
+// g C .. g C + C - 1 (C = RANKS::kCount); a row whose range needs all 32 bits,
+// or a row with a target past the window, takes stream_select on its own.
+constexpr uint32_t kGroupMaxN = 255;
+constexpr int kGroupGL = 16;
+constexpr uint32_t kGroupRows = kWave / kGroupGL;
+
+__device__ __forceinline__ uint32_t group16_min(uint32_t v) {
+  v = min(v, dpp<kDppXor1>(v));
+  v = min(v, dpp<kDppXor2>(v));
+  v = min(v, dpp<kDppHalfMirror>(v));
+  return min(v, dpp<kDppMirror>(v));
+}
+__device__ __forceinline__ uint32_t group16_max(uint32_t v) {
+  v = max(v, dpp<kDppXor1>(v));
+  v = max(v, dpp<kDppXor2>(v));
+  v = max(v, dpp<kDppHalfMirror>(v));
+  return max(v, dpp<kDppMirror>(v));
+}
+__device__ __forceinline__ uint32_t group16_sum(uint32_t v) {
+  v += dpp<kDppXor1>(v);
+  v += dpp<kDppXor2>(v);
+  v += dpp<kDppHalfMirror>(v);
+  return v + dpp<kDppMirror>(v);
+}
+
+// Rows begin .. end - 1 of one series (rows of N <= kGroupMaxN samples from
+// element off0), four per step; emit(i, o, first) gets row i's results with
+// its targets on lanes first .. first + C - 1 of o.sel.
+template <class RANKS, class Emit>
+__device__ __forceinline__ void select_rows_grouped(RowLds& L, const uint32_t* __restrict__ samples, uint64_t off0,
+                                                    uint32_t N, uint32_t begin, uint32_t end, uint32_t lane,
+                                                    Emit&& emit) {
+  constexpr uint32_t C = RANKS::kCount;
+  constexpr int GL = kGroupGL;
+  static_assert(kGroupRows * C <= (uint32_t)kWave, "every row's targets have lanes");
+  if (begin >= end) return;
+  const uint32_t g = lane / GL, gl = lane % GL;
+  const uint32_t nqu = min(4u, ((N >> 2) + GL - 1) / GL);
+  const bool tl = lane < kGroupRows * C;         // a target lane: row tg, rank j
+  const uint32_t tg = tl ? lane / C : 0u;
+  const uint32_t R = tl ? RANKS::rank(lane % C, N) : 0u;
+  uint32_t* hist = L.hist;
+  u32x4* hv = reinterpret_cast<u32x4*>(hist);
+  Batch cur;
+  load_group<GL>(cur, samples, off0 + (uint64_t)(begin + g) * N, N, begin + g < end, gl, nqu);
+  for (uint32_t i = begin; i < end; i += kGroupRows) {
+    const uint32_t nrows = min(kGroupRows, end - i);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hv[lane * 4 + q] = u32x4{0u, 0u, 0u, 0u};
+    uint32_t mn = 0xffffffffu, mx = 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if ((cur.m >> u) & 1u) {
+        const u32x4 v = cur.q[u];
+        mn = min(mn, min(min(v.x, v.y), min(v.z, v.w)));
+        mx = max(mx, max(max(v.x, v.y), max(v.z, v.w)));
+      }
+    if (cur.m & 16u) {
+      mn = min(mn, cur.x);
+      mx = max(mx, cur.x);
+    }
+    const uint32_t rmin = group16_min(mn), rmax = group16_max(mx);
+    const bool has = g < nrows;  // every row of the step has N >= 1 samples
+    const uint32_t range = has ? rmax - rmin : 0u;
+    const uint32_t b = range ? 32u - __clz(range) : 0u;
+    const uint32_t inc = 1u << (8u * g);
+    const bool wide = ballot(has && b > kFastBits) != 0;
+    uint64_t s1 = 0, s2 = 0;
+    uint32_t s2h = 0;
+    wave_lds_sync();  // the window is clear before any count
+    if (!wide) {
+      // keys z = r - rmin below 2^13: per lane at most 17 of them (t2 < 2^31),
+      // per row sum z < 2^21 and sum z^2 < 2^34, the latter summed as its low
+      // 16 bits and the rest
+      uint32_t t1 = 0, t2 = 0;
+      auto one = [&](uint32_t x) {
+        const uint32_t z = x - rmin;
+        t1 += z;
+        t2 = __umul24(z, z) + t2;
+        atomicAdd(&hist[min(z, kSelWin - 1u)], inc);
+      };
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if ((cur.m >> u) & 1u) {
+          one(cur.q[u].x);
+          one(cur.q[u].y);
+          one(cur.q[u].z);
+          one(cur.q[u].w);
+        }
+      if (cur.m & 16u) one(cur.x);
+      const uint32_t a = group16_sum(t1), lo = group16_sum(t2 & 0xffffu), hi = group16_sum(t2 >> 16);
+      const uint64_t T2 = (uint64_t)lo + ((uint64_t)hi << 16);
+      const u128 q2 = (u128)T2 + (u128)(2ull * rmin) * a + (u128)((uint64_t)rmin * rmin) * N;
+      s1 = (uint64_t)a + (uint64_t)rmin * N;
+      s2 = (uint64_t)q2;
+      s2h = (uint32_t)(q2 >> 64);
+    } else {
+      uint32_t unused = 0xffffffffu;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if ((cur.m >> u) & 1u) acc_quad(cur.q[u], unused, s1, s2, s2h);
+      if (cur.m & 16u) acc_sample(cur.x, unused, s1, s2, s2h);
+      group_total_64_96<GL>(s1, s2, s2h);
+      if (b < 32) {
+        auto one = [&](uint32_t x) { atomicAdd(&hist[min(x - rmin, kSelWin - 1u)], inc); };
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if ((cur.m >> u) & 1u) {
+            one(cur.q[u].x);
+            one(cur.q[u].y);
+            one(cur.q[u].z);
+            one(cur.q[u].w);
+          }
+        if (cur.m & 16u) one(cur.x);
+      }
+    }
+    // the next step's rows are in flight while this step's order statistics are found
+    const uint32_t nx = i + kGroupRows;
+    if (nx < end) load_group<GL>(cur, samples, off0 + (uint64_t)(nx + g) * N, N, nx + g < end, gl, nqu);
+    // the window of the four rows: lane totals, wave scan, each target's owner lane
+    wave_lds_sync();
+    uint32_t t = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const u32x4 v = hv[lane * 4 + q];
+      t += v.x + v.y + v.z + v.w;
+    }
+    const uint32_t incl = wave_incl_scan(t);
+    uint32_t owner = 0;
+#pragma unroll
+    for (uint32_t rg = 0; rg < kGroupRows; ++rg) {
+      const uint32_t f = (incl >> (8u * rg)) & 0xffu;
+#pragma unroll
+      for (uint32_t j = 0; j < C; ++j) {
+        const uint64_t m = ballot(f > RANKS::rank(j, N));  // empty for a row without a window
+        const uint32_t o = m ? (uint32_t)__builtin_ctzll(m) : 0u;
+        if (lane == rg * C + j) owner = o;
+      }
+    }
+    const uint32_t sh = 8u * tg;
+    const uint32_t below = ((uint32_t)__shfl((int)(incl - t), (int)owner) >> sh) & 0xffu;
+    uint32_t key = 0, r = 0;
+    bool last = false;
+    if (tl) {
+      r = R - below;
+      uint32_t cum = 0, nb = 0, under = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const u32x4 v = hv[owner * 4 + q];
+        const uint32_t c[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          cum += (c[e] >> sh) & 0xffu;
+          const bool le = cum <= r;
+          nb += le ? 1u : 0u;
+          under = le ? cum : under;
+        }
+      }
+      key = owner * 16u + nb;
+      r -= under;
+      last = key == kSelWin - 1u;
+    }
+    wave_lds_sync();
+    // each row's results; radix levels for a row without a window or with a
+    // target past it (both rare for latency rows)
+    for (uint32_t rg = 0; rg < nrows; ++rg) {
+      const int src = (int)(rg * GL);
+      RowOut o;
+      o.rmin = (uint32_t)__builtin_amdgcn_readlane((int)rmin, src);
+      o.rmax = (uint32_t)__builtin_amdgcn_readlane((int)rmax, src);
+      o.s1 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(s1 >> 32), src) << 32) |
+             (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)s1, src);
+      o.s2 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(s2 >> 32), src) << 32) |
+             (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)s2, src);
+      o.s2h = (uint32_t)__builtin_amdgcn_readlane((int)s2h, src);
+      const uint32_t bb = (uint32_t)__builtin_amdgcn_readlane((int)b, src);
+      const bool mine = tl && tg == rg;
+      o.sel = key + o.rmin;
+      if (bb >= 32) {
+        const RowGeo gr = row_geo(samples, off0 + (uint64_t)(i + rg) * N, N);
+        const uint32_t kk = stream_select(L, samples, gr, o.rmin, 0u, 32u, R, mine, lane);
+        if (mine) o.sel = kk + o.rmin;
+      } else if (ballot(mine && last) != 0) {
+        const RowGeo gr = row_geo(samples, off0 + (uint64_t)(i + rg) * N, N);
+        const uint32_t offk = kSelWin - 1u;
+        const uint32_t top = o.rmax - o.rmin - offk;
+        const uint32_t bits = top ? 32u - __clz(top) : 1u;
+        const uint32_t kk = stream_select(L, samples, gr, o.rmin, offk, bits, r, mine && last, lane);
+        if (mine && last) o.sel = kk + offk + o.rmin;
+      }
+      emit(i + rg, o, rg * C);
+    }
+  }
+}
+
+// Row class of the order-statistics kernels: rows of up to kGroupMaxN samples
+// go four to a wave (class kGrouped); otherwise a row of N samples needs
+// ceil(floor(N / 4) / 256) load batches at most, and rows of up to 1, 2 or 4
+// of them are held in registers (class 1, 2, 4), longer rows are streamed
 // (class kStreamed).
-constexpr uint32_t kStreamed = 8;
 // Waves per SIMD the row-pass kernels are compiled for, by row class (1 = the
 // compiler's choice). With 4.3 KiB of LDS per wave the register file sets the
-// occupancy; these are the largest targets met without spills (feature pass:
-// 6 at 80 registers; statistics pass: 7 at 72), which run rows of up to 1027
-// samples 6% and 9% faster than the 5 waves the compiler picks by itself.
-// Rows of 2048 samples keep the compiler's 4 (5 spills and runs slower).
+// occupancy; these are the largest targets met without spills (6 at 80
+// registers), which run rows of up to 1027 samples 6 - 9% faster than the 5
+// waves the compiler picks by itself. Rows of 2048 samples and short rows
+// keep the compiler's 4 (more spill and run slower).
 __host__ __device__ constexpr int feat_waves_per_eu(int NB) { return NB == 1 ? 6 : NB == 4 ? 3 : 1; }
-__host__ __device__ constexpr int stats_waves_per_eu(int NB) { return NB == 1 ? 7 : 1; }
+__host__ __device__ constexpr int stats_waves_per_eu(int NB) { return NB == 1 ? 6 : 1; }
 __host__ __device__ constexpr uint32_t feat_batches(uint32_t N) {
-  return (N / 4 + 4u * kWave - 1) / (4u * kWave) <= 1
+  return N <= kGroupMaxN ? kGrouped
+         : (N / 4 + 4u * kWave - 1) / (4u * kWave) <= 1
              ? 1u
              : ((N / 4 + 4u * kWave - 1) / (4u * kWave) <= 2
                     ? 2u

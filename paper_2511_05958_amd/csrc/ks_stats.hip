@@ -48,8 +48,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_w
                                                         uint64_t out_rows) {
   constexpr int W = 4;
   constexpr uint32_t kStage = 16;  // rows per contiguous write of a wave's records
+  // a row's exact results, staged until kStage rows are done; the records
+  // (mean, std in FP64) are then made by kStage lanes at once
+  struct RowStage {
+    uint64_t s1[kStage], s2[kStage];
+    uint32_t s2h[kStage], rmin[kStage], rmax[kStage], p50[kStage], p95[kStage];
+  };
   __shared__ ks::RowLds sel[W];
-  __shared__ __align__(16) uint32_t stage[W][kStage * 8];
+  __shared__ RowStage stage[W];
   const uint32_t s = blockIdx.x;
   if (s >= num_series) return;
   const ks_desc d = desc[s];
@@ -70,29 +76,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_w
   // interleaved row by row, left partly written cache lines behind)
   const uint32_t B = (K + W - 1) / W;
   const uint32_t begin = min(w * B, K), end = min(begin + B, K);
-  uint32_t* st = stage[w];
-  auto emit = [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t rmin, uint32_t rmax, uint32_t sel_x) {
-    const uint32_t p95 = (uint32_t)__builtin_amdgcn_readlane((int)sel_x, 1);
+  RowStage& st = stage[w];
+  // row i's results; its p50 and p95 on lanes first and first + 1 of sel_x
+  auto emit = [&](uint32_t i, uint64_t s1, uint64_t s2, uint32_t s2h, uint32_t rmin, uint32_t rmax, uint32_t sel_x,
+                  uint32_t first) {
+    const uint32_t p50 = (uint32_t)__builtin_amdgcn_readlane((int)sel_x, (int)first);
+    const uint32_t p95 = (uint32_t)__builtin_amdgcn_readlane((int)sel_x, (int)first + 1);
     const uint32_t j = (i - begin) % kStage;
     if (lane == 0) {
-      const u128 S2 = ((u128)s2h << 64) | s2;
-      const u128 num = (u128)N * S2 - (u128)s1 * s1;  // >= 0 (Cauchy-Schwarz), < 2^113
-      const double nn = (double)N * (double)N;
-      const ks_row_stats r{(double)s1 / (double)N, sqrt(u128_to_double(num) / nn), rmin, sel_x, p95, rmax};
-      *reinterpret_cast<ks_row_stats*>(st + j * 8) = r;
+      st.s1[j] = s1;
+      st.s2[j] = s2;
+      st.s2h[j] = s2h;
+      st.rmin[j] = rmin;
+      st.rmax[j] = rmax;
+      st.p50[j] = p50;
+      st.p95[j] = p95;
     }
-    if (j + 1 == kStage || i + 1 == end) {  // flush rows i - j .. i
+    if (j + 1 == kStage || i + 1 == end) {  // rows i - j .. i: lane q makes row i - j + q's record
       ks::wave_lds_sync();
-      if (lane < 2 * (j + 1))
-        ks::row_out_store<NB>(reinterpret_cast<const ks::u32x4*>(st)[lane],
-                              &reinterpret_cast<ks::u32x4*>(o + (i - j))[lane]);
+      if (lane <= j) {
+        const uint64_t a1 = st.s1[lane];
+        const u128 S2 = ((u128)st.s2h[lane] << 64) | st.s2[lane];
+        const u128 num = (u128)N * S2 - (u128)a1 * a1;  // >= 0 (Cauchy-Schwarz), < 2^113
+        const double nn = (double)N * (double)N;
+        const ks_row_stats r{(double)a1 / (double)N, sqrt(u128_to_double(num) / nn), st.rmin[lane], st.p50[lane],
+                             st.p95[lane], st.rmax[lane]};
+        static_assert(sizeof(ks_row_stats) == 32, "a record is two 16-byte stores");
+        ks::u32x4 v0, v1;
+        __builtin_memcpy(&v0, &r, 16);
+        __builtin_memcpy(&v1, reinterpret_cast<const char*>(&r) + 16, 16);
+        ks::u32x4* dst = reinterpret_cast<ks::u32x4*>(o + (i - j) + lane);
+        ks::row_out_store<NB>(v0, dst);
+        ks::row_out_store<NB>(v1, dst + 1);
+      }
       ks::wave_lds_sync();
     }
   };
   if constexpr (NB == (int)ks::kStreamed) {
     ks::select_rows_long<StatRanks>(L, samples, d.offset, N, end, begin, 1u, lane, [&](uint32_t i, const ks::RowOut& r) {
-      emit(i, r.s1, r.s2, r.s2h, r.rmin, r.rmax, r.sel);
+      emit(i, r.s1, r.s2, r.s2h, r.rmin, r.rmax, r.sel, 0u);
     });
+  } else if constexpr (NB == (int)ks::kGrouped) {
+    ks::select_rows_grouped<StatRanks>(L, samples, d.offset, N, begin, end, lane,
+                                       [&](uint32_t i, const ks::RowOut& r, uint32_t first) {
+                                         emit(i, r.s1, r.s2, r.s2h, r.rmin, r.rmax, r.sel, first);
+                                       });
   } else {
     ks::Batch cur[NB];
     ks::RowGeo g;
@@ -104,7 +132,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_w
       // the next row's loads are in flight while this row's percentiles are found
       const ks::RowGeo gi = g;
       if (i + 1 < end) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)(i + 1) * N, N, lane);
-      emit(i, s1, s2, s2h, rs.rmin, rs.rmax, ks::row_select<NB, StatRanks>(L, samples, gi, rs, N, lane));
+      emit(i, s1, s2, s2h, rs.rmin, rs.rmax, ks::row_select<NB, StatRanks>(L, samples, gi, rs, N, lane), 0u);
     }
   }
 }
@@ -121,8 +149,9 @@ extern "C" int ks_stats_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t num
   DeviceGuard g(ctx->device);
   if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  // one launch per row class (1, 2 or 4 load batches per row, or streamed); each
-  // workgroup whose series belongs to another class returns at once
+  // one launch per row class (1, 2 or 4 load batches per row, streamed, or
+  // short rows four to a wave); each workgroup whose series belongs to another
+  // class returns at once
   hipLaunchKernelGGL(row_stats_kernel<1>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
                      max_K, out, out_rows);
   hipLaunchKernelGGL(row_stats_kernel<2>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
@@ -130,6 +159,8 @@ extern "C" int ks_stats_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t num
   hipLaunchKernelGGL(row_stats_kernel<4>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
                      max_K, out, out_rows);
   hipLaunchKernelGGL(row_stats_kernel<ks::kStreamed>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc,
+                     num_series, max_K, out, out_rows);
+  hipLaunchKernelGGL(row_stats_kernel<ks::kGrouped>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc,
                      num_series, max_K, out, out_rows);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? KS_OK : hip_fail(e, "row stats launch");

@@ -106,8 +106,9 @@ def test_features_edge_cases(ctx):
 
 
 def _select_stress_series():
-    """Rows that exercise every row-length class (1, 2 or 4 load batches), rows
-    that start off a 16-byte boundary, and ranges needing 1..5 digit levels."""
+    """Rows that exercise every row-length class (short rows four to a wave, 1,
+    2 or 4 load batches), rows that start off a 16-byte boundary, and ranges
+    needing 1..5 digit levels."""
     rng = np.random.default_rng(20251105)
     out = []
     Ns = [1, 2, 3, 5, 63, 64, 65, 1023, 1027, 1028, 1029, 2051, 2052, 2053, 4095, 4096]
@@ -140,6 +141,25 @@ def _select_stress_series():
     # keys at the window's last unit bin and just past it
     for N in (257, 2049):
         out.append((300 + rng.choice(np.array([0, 1, 1021, 1022, 1023, 1024, 1025]), (2, N))).astype(np.uint32))
+    # short rows, four to a wave: several steps with a partial last one, rows of
+    # every kind side by side (latency-like, full 32-bit range, upper deciles
+    # past the window, constant, a single sample)
+    for N, K in ((255, 9), (200, 10), (4, 13), (1, 7)):
+        base = rng.lognormal(np.log(700), 0.08, (K, N))
+        r = np.round(base * np.where(rng.random((K, N)) < 0.02, rng.uniform(1, 5, (K, N)), 1.0))
+        out.append(np.asarray(r, np.uint64).astype(np.uint32))
+    mixed = np.empty((11, 250), np.uint64)
+    for k in range(11):
+        kind = k % 4
+        if kind == 0:
+            mixed[k] = rng.integers(0, 1 << 32, 250, dtype=np.uint64)
+        elif kind == 1:
+            mixed[k] = np.where(rng.random(250) < 0.55, rng.integers(200, 260, 250), 200 + rng.integers(2_000, 2_000_000, 250))
+        elif kind == 2:
+            mixed[k] = 4321
+        else:
+            mixed[k] = rng.integers(900, 1100, 250)
+    out.append(mixed.astype(np.uint32))
     return out
 
 
