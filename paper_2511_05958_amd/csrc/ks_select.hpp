@@ -1062,8 +1062,9 @@ __device__ __forceinline__ void select_rows_grouped(RowLds& L, const uint32_t* _
 // compiler's choice). With 4.3 KiB of LDS per wave the register file sets the
 // occupancy; these are the largest targets met without spills (6 at 80
 // registers), which run rows of up to 1027 samples 6 - 9% faster than the 5
-// waves the compiler picks by itself. Rows of 2048 samples and short rows
-// keep the compiler's 4 (more spill and run slower).
+// waves the compiler picks by itself. Rows of 2048 samples keep the
+// compiler's 4 (5 spills and runs slower), and so do short rows (higher
+// targets spill).
 __host__ __device__ constexpr int feat_waves_per_eu(int NB) { return NB == 1 ? 6 : NB == 4 ? 3 : 1; }
 __host__ __device__ constexpr int stats_waves_per_eu(int NB) { return NB == 1 ? 6 : 1; }
 __host__ __device__ constexpr uint32_t feat_batches(uint32_t N) {
