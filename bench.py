@@ -604,7 +604,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["copy", "ceiling", "rowlen"])
     ap.add_argument("--extra", default="c2,c3",
-                    help="comma-separated workloads whose plain scan and learned leg are added under 'workloads' "
+                    help="comma-separated workloads whose plain scan, learned leg and statistics leg are added under 'workloads' "
                          "('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="autotune",
@@ -698,6 +698,9 @@ def main() -> int:
         mp = os.path.join(MODEL_DIR, MODELS.get(w, "proposal_r4.ckpt"))
         if not args.no_learned and os.path.exists(mp) and b.specs["N"].max() <= P.KS_FEATURE_MAX_N:
             r["learned"] = learned_leg(args, ctx, b, s_, d_, p_, stream, res_, r["value"], mp)
+        if not args.no_stats and b.specs["N"].max() <= P.KS_FEATURE_MAX_N:
+            r["row_stats"], so_ = stats_leg(args, b, s_, d_, p_, ctx, stream)
+            del so_
         line["workloads"][w] = r
         del s_, d_, o_
         torch.cuda.empty_cache()
