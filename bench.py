@@ -604,8 +604,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["copy", "ceiling", "rowlen"])
     ap.add_argument("--extra", default="c2,c3",
-                    help="comma-separated workloads whose plain scan, learned leg and statistics leg are added under 'workloads' "
-                         "('' for none)")
+                    help="comma-separated workloads whose plain scan, learned leg and statistics leg are added "
+                         "under 'workloads' ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--launch", default="autotune",
                     choices=["autotune", "default", "grid", "ordered", "persistent", "persistent-direct"],
