@@ -450,6 +450,9 @@ typedef struct ks_row_stats {
  *   out       device, ks_row_stats[out_rows]
  * A series that ks_scan_batch would flag (KS_BAD_SHAPE, KS_OUT_OF_RANGE), or
  * with N > KS_FEATURE_MAX_N, writes mean = std = NaN and zeros for its rows.
+ * The series' order per row class (longest first) is kept in the context's
+ * scan workspace, which grows to num_series series as with ks_reserve
+ * (KS_E_NOMEM when the device is full).
  * KS_E_INVALID on a NULL pointer, KS_E_RANGE on max_K outside [2,
  * KS_MAX_K]. */
 int ks_stats_batch(ks_ctx *ctx, const uint32_t *samples, uint64_t num_samples, const ks_desc *desc,

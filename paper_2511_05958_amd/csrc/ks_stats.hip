@@ -9,6 +9,7 @@
 
 #include "ks.h"
 #include "ks_ctx.hpp"
+#include "ks_plan.hpp"
 #include "ks_scan.hpp"
 #include "ks_select.hpp"
 
@@ -45,7 +46,7 @@ template <int NB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_waves_per_eu(NB)))) void row_stats_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                         const ks_desc* __restrict__ desc, uint32_t num_series,
                                                         uint32_t max_K, ks_row_stats* __restrict__ out,
-                                                        uint64_t out_rows) {
+                                                        uint64_t out_rows, const uint32_t* __restrict__ plan) {
   constexpr int W = 4;
   constexpr uint32_t kStage = 16;  // rows per contiguous write of a wave's records
   // a row's exact results, staged until kStage rows are done; the records
@@ -56,8 +57,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_w
   };
   __shared__ ks::RowLds sel[W];
   __shared__ RowStage stage[W];
-  const uint32_t s = blockIdx.x;
-  if (s >= num_series) return;
+  // workgroup t takes the t-th series of this row class in the plan's order
+  // (largest first; malformed series in class 1)
+  const uint32_t ci = ks::feat_class_index(NB);
+  if (blockIdx.x >= plan[num_series + ks::kFeatClasses + ci]) return;
+  const uint32_t s = plan[plan[num_series + ci] + blockIdx.x];
   const ks_desc d = desc[s];
   const uint32_t lane = ks::lane_id(), w = ks::wave_id();
   const bool bad = ks::check_desc(d, num_samples, max_K) || d.N > KS_FEATURE_MAX_N;
@@ -149,19 +153,24 @@ extern "C" int ks_stats_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t num
   DeviceGuard g(ctx->device);
   if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  // one launch per row class (1, 2 or 4 load batches per row, streamed, or
-  // short rows four to a wave); each workgroup whose series belongs to another
-  // class returns at once
+  // the series order per row class (the feature pass's plan), kept in the
+  // context's scan workspace (its queue items: 512 bytes per series); then one
+  // launch per row class (1, 2 or 4 load batches per row, streamed, or short
+  // rows four to a wave), each taking its own series largest first
+  if (int rc = ks_reserve(ctx, num_series, 0)) return rc;
+  uint32_t* plan = reinterpret_cast<uint32_t*>(ctx->items);
+  hipLaunchKernelGGL(ks::feature_plan_kernel, dim3(1), dim3(ks::kFeatPlanNT), 0, st, desc, num_series, num_samples,
+                     max_K, plan);
   hipLaunchKernelGGL(row_stats_kernel<1>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
-                     max_K, out, out_rows);
+                     max_K, out, out_rows, (const uint32_t*)plan);
   hipLaunchKernelGGL(row_stats_kernel<2>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
-                     max_K, out, out_rows);
+                     max_K, out, out_rows, (const uint32_t*)plan);
   hipLaunchKernelGGL(row_stats_kernel<4>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
-                     max_K, out, out_rows);
+                     max_K, out, out_rows, (const uint32_t*)plan);
   hipLaunchKernelGGL(row_stats_kernel<ks::kStreamed>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc,
-                     num_series, max_K, out, out_rows);
+                     num_series, max_K, out, out_rows, (const uint32_t*)plan);
   hipLaunchKernelGGL(row_stats_kernel<ks::kGrouped>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc,
-                     num_series, max_K, out, out_rows);
+                     num_series, max_K, out, out_rows, (const uint32_t*)plan);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? KS_OK : hip_fail(e, "row stats launch");
 }
