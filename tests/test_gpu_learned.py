@@ -144,7 +144,7 @@ def _select_stress_series():
     # short rows, four to a wave: several steps with a partial last one, rows of
     # every kind side by side (latency-like, full 32-bit range, upper deciles
     # past the window, constant, a single sample)
-    for N, K in ((255, 9), (200, 10), (4, 13), (1, 7)):
+    for N, K in ((255, 9), (200, 10), (4, 13), (1, 7), (256, 5), (384, 7)):
         base = rng.lognormal(np.log(700), 0.08, (K, N))
         r = np.round(base * np.where(rng.random((K, N)) < 0.02, rng.uniform(1, 5, (K, N)), 1.0))
         out.append(np.asarray(r, np.uint64).astype(np.uint32))
@@ -160,6 +160,19 @@ def _select_stress_series():
         else:
             mixed[k] = rng.integers(900, 1100, 250)
     out.append(mixed.astype(np.uint32))
+    # the same mix on rows of one load batch
+    mixed2 = np.empty((9, 450), np.uint64)
+    for k in range(9):
+        kind = k % 4
+        if kind == 0:
+            mixed2[k] = np.where(rng.random(450) < 0.55, rng.integers(200, 260, 450), 200 + rng.integers(2_000, 2_000_000, 450))
+        elif kind == 1:
+            mixed2[k] = rng.integers(0, 1 << 32, 450, dtype=np.uint64)
+        elif kind == 2:
+            mixed2[k] = rng.integers(900, 1100, 450)
+        else:
+            mixed2[k] = 77
+    out.append(mixed2.astype(np.uint32))
     return out
 
 
