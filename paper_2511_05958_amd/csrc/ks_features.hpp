@@ -107,14 +107,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
     Batch cur[NB];
     RowGeo g;
     if (begin < end) g = load_row<NB>(cur, samples, d.offset + (uint64_t)begin * N, N, lane);
+    uint32_t p = 0;  // window base from the previous row (none for the first)
     for (uint32_t i = begin; i < end; ++i) {
       uint64_t s1, s2;
       uint32_t s2h;
-      const RowScan rs = row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
+      RowScan rs;
+      const bool based = i > begin && row_scan_based<NB>(L, cur, g, N, p, s1, s2, s2h, rs, lane);
+      if (!based) rs = row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
       // the next row's loads are in flight while this row's order statistics are found
       const RowGeo gi = g;
       if (i + 1 < end) g = load_row<NB>(cur, samples, d.offset + (uint64_t)(i + 1) * N, N, lane);
-      emit(i, s1, s2, s2h, rs.rmin, row_select<NB, DecileRanks>(L, samples, gi, rs, N, lane), 0u);
+      const uint32_t sel = based ? select_from_window<DecileRanks>(L, samples, gi, p, rs.rmax, N, lane)
+                                 : row_select<NB, DecileRanks>(L, samples, gi, rs, N, lane);
+      p = rs.rmin > kRowMargin ? rs.rmin - kRowMargin : 0u;
+      emit(i, s1, s2, s2h, rs.rmin, sel, 0u);
     }
   }
   if (lane == 0) red[w] = gmin;

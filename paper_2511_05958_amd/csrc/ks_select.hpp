@@ -523,6 +523,60 @@ __device__ __forceinline__ RowScan row_scan(RowLds& L, const Batch (&B)[NB], con
   return rs;
 }
 
+// The same for a row whose window is based at p, a provisional base (the
+// previous row's minimum less kRowMargin): one pass over the registers takes
+// the minimum and maximum, sums k = r - p and k^2 in 32 bits per batch and
+// counts every key, so the counting does not wait for the row's minimum. It
+// holds when the row's minimum is >= p and its maximum - p < 2^kFastBits;
+// false otherwise (moments and window are then not valid, the caller runs
+// row_scan on the registers, which are still intact).
+constexpr uint32_t kRowMargin = 128;
+
+template <int NB>
+__device__ __forceinline__ bool row_scan_based(RowLds& L, const Batch (&B)[NB], const RowGeo& g, uint32_t N,
+                                               uint32_t p, uint64_t& s1, uint64_t& s2, uint32_t& s2h, RowScan& rs,
+                                               uint32_t lane) {
+  u32x4* hv = reinterpret_cast<u32x4*>(L.hist);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) hv[lane * 4 + i] = u32x4{0u, 0u, 0u, 0u};
+  wave_lds_sync();
+  uint32_t* hist = L.hist;
+  uint32_t mn = 0xffffffffu, mx = 0u, t1 = 0, t2b = 0;
+  uint64_t t2 = 0;
+  auto one = [&](uint32_t x) {
+    mn = min(mn, x);
+    mx = max(mx, x);
+    const uint32_t z = x - p;  // wraps for x < p: the row is then rejected below
+    t1 += z;
+    t2b = __umul24(z, z) + t2b;
+    atomicAdd(&hist[min(z, kSelWin - 1u)], 1u);
+  };
+  for_row(
+      B, g,
+      [&](const u32x4& v) {
+        one(v.x);
+        one(v.y);
+        one(v.z);
+        one(v.w);
+      },
+      one,
+      [&] {
+        t2 += t2b;
+        t2b = 0;
+      });
+  rs.rmin = wave_min_u32(mn);
+  rs.rmax = wave_max_u32(mx);
+  const uint32_t range = rs.rmax - rs.rmin;
+  rs.b = range ? 32u - __clz(range) : 0u;
+  if (rs.rmin < p || rs.rmax - p >= (1u << kFastBits)) return false;
+  wave_total_fast_moments(t1, t2);
+  const u128 q2 = (u128)t2 + (u128)(2ull * p) * t1 + (u128)((uint64_t)p * p) * N;
+  s1 = (uint64_t)t1 + (uint64_t)p * N;
+  s2 = (uint64_t)q2;
+  s2h = (uint32_t)(q2 >> 64);
+  return true;
+}
+
 // MSD radix levels over the keys k = r - m - off of the row's samples with
 // r - m >= off (m = rmin), for targets (lanes with tl, at most kSelNone of
 // them, consecutive, ranks R non-decreasing with the lane; R counts among

@@ -129,14 +129,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_w
     ks::Batch cur[NB];
     ks::RowGeo g;
     if (begin < end) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)begin * N, N, lane);
+    uint32_t p = 0;  // window base from the previous row (none for the first)
     for (uint32_t i = begin; i < end; ++i) {
       uint64_t s1, s2;
       uint32_t s2h;
-      const ks::RowScan rs = ks::row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
+      ks::RowScan rs;
+      const bool based = i > begin && ks::row_scan_based<NB>(L, cur, g, N, p, s1, s2, s2h, rs, lane);
+      if (!based) rs = ks::row_scan<NB>(L, cur, g, N, s1, s2, s2h, lane);
       // the next row's loads are in flight while this row's percentiles are found
       const ks::RowGeo gi = g;
       if (i + 1 < end) g = ks::load_row<NB>(cur, samples, d.offset + (uint64_t)(i + 1) * N, N, lane);
-      emit(i, s1, s2, s2h, rs.rmin, rs.rmax, ks::row_select<NB, StatRanks>(L, samples, gi, rs, N, lane), 0u);
+      const uint32_t sel = based ? ks::select_from_window<StatRanks>(L, samples, gi, p, rs.rmax, N, lane)
+                                 : ks::row_select<NB, StatRanks>(L, samples, gi, rs, N, lane);
+      p = rs.rmin > ks::kRowMargin ? rs.rmin - ks::kRowMargin : 0u;
+      emit(i, s1, s2, s2h, rs.rmin, rs.rmax, sel, 0u);
     }
   }
 }
