@@ -27,12 +27,18 @@ struct LearnWs {
 // block of rows and writes every kFeatStage rows' deciles and moments as
 // contiguous stores (rows written one at a time, by waves interleaved row by
 // row, left partly written cache lines behind; they cost 5 - 15% of the
-// pass and made its time depend on where the buffers lay in memory).
-constexpr uint32_t kFeatStage = 16;
+// pass and made its time depend on where the buffers lay in memory). Rows of
+// two or more load batches stage 64 rows (fewer, longer write bursts among
+// the reads: the learned step on 8192 x 1024 x 2048 ran 1 - 4% faster than
+// with 16); one-batch and short rows stage 16, which keeps their LDS within
+// six workgroups per CU.
+__host__ __device__ constexpr uint32_t feat_stage_rows(int NB) { return NB == 1 || NB == (int)kGrouped ? 16u : 64u; }
+
+template <uint32_t S>
 struct FeatStage {
-  uint32_t dec[kFeatStage * 9];
-  uint64_t s1[kFeatStage], s2lo[kFeatStage];
-  uint32_t s2hi[kFeatStage];
+  uint32_t dec[S * 9];
+  uint64_t s1[S], s2lo[S];
+  uint32_t s2hi[S];
 };
 
 // First step, workgroup t of the launch of row class NB (rows in 1, 2 or 4
@@ -50,7 +56,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
                                                       const uint32_t* __restrict__ plan) {
   constexpr int W = NT / kWave;
   __shared__ RowLds sel[W];
-  __shared__ FeatStage stage[W];
+  constexpr uint32_t kFeatStage = feat_stage_rows(NB);
+  __shared__ FeatStage<kFeatStage> stage[W];
   __shared__ uint32_t red[W];
   const uint32_t ci = feat_class_index(NB);
   if (blockIdx.x >= plan[num_series + kFeatClasses + ci]) return;
@@ -67,7 +74,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
   const uint32_t K = d.K, N = d.N;
   const uint64_t slot = (uint64_t)s * SR + 2;
   RowLds& L = sel[w];
-  FeatStage& st = stage[w];
+  FeatStage<kFeatStage>& st = stage[w];
   const uint32_t B = (K + W - 1) / W;
   const uint32_t begin = min(w * B, K), end = min(begin + B, K);
   uint32_t gmin = 0xffffffffu;

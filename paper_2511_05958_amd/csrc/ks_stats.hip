@@ -48,7 +48,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_w
                                                         uint32_t max_K, ks_row_stats* __restrict__ out,
                                                         uint64_t out_rows, const uint32_t* __restrict__ plan) {
   constexpr int W = 4;
-  constexpr uint32_t kStage = 16;  // rows per contiguous write of a wave's records
+  // rows per contiguous write of a wave's records (64 for rows of two or more
+  // load batches: fewer, longer write bursts among the reads)
+  constexpr uint32_t kStage = NB == 1 || NB == (int)ks::kGrouped ? 16u : 64u;
   // a row's exact results, staged until kStage rows are done; the records
   // (mean, std in FP64) are then made by kStage lanes at once
   struct RowStage {
