@@ -32,6 +32,7 @@ struct LearnWs {
 // the reads: the learned step on 8192 x 1024 x 2048 ran 1 - 4% faster than
 // with 16); one-batch and short rows stage 16, which keeps their LDS within
 // six workgroups per CU.
+// (at most 64: a flush writes one row's moments per lane)
 __host__ __device__ constexpr uint32_t feat_stage_rows(int NB) { return NB == 1 || NB == (int)kGrouped ? 16u : 64u; }
 
 template <uint32_t S>
@@ -57,6 +58,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(feat_waves_p
   constexpr int W = NT / kWave;
   __shared__ RowLds sel[W];
   constexpr uint32_t kFeatStage = feat_stage_rows(NB);
+  static_assert(kFeatStage <= (uint32_t)kWave, "a flush writes one row's moments per lane");
   __shared__ FeatStage<kFeatStage> stage[W];
   __shared__ uint32_t red[W];
   const uint32_t ci = feat_class_index(NB);

@@ -51,6 +51,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_w
   // rows per contiguous write of a wave's records (64 for rows of two or more
   // load batches: fewer, longer write bursts among the reads)
   constexpr uint32_t kStage = NB == 1 || NB == (int)ks::kGrouped ? 16u : 64u;
+  static_assert(kStage <= (uint32_t)ks::kWave, "a flush makes one record per lane");
   // a row's exact results, staged until kStage rows are done; the records
   // (mean, std in FP64) are then made by kStage lanes at once
   struct RowStage {
