@@ -1,8 +1,8 @@
 // Learned-proposal stage 1: one read of every sample gives, per row,
 //   - the moments (sum r, sum r^2) that the exact refine turns into eq. 2 keys,
-//   - the nine deciles x_(floor(k (N-1) / 10)), k = 1..9, by a wave-level
-//     radix select over the row's uint32 cycle counts (keys r - row minimum,
-//     as many digit levels as the row's range needs),
+//   - the nine deciles x_(floor(k (N-1) / 10)), k = 1..9, by the wave-level
+//     select of ks_select.hpp (a 1024-bin window of the keys above the row's
+//     minimum or a base just below it, radix levels only past the window),
 // and per series the minimum m, then features f = (double)(x - m) / max(m, 1)
 // rounded to float (project-defined inputs of the network).
 #pragma once
