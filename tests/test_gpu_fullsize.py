@@ -118,3 +118,49 @@ def test_series_above_4gib_among_small_ones(launch):
         assert g[t]["flags"] == (P.KS_SIGNIFICANT if o["significant"] else 0), t
     del buf
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("recipe,how", [(5, "autotune"), (5, "persistent-16MiB-v2"), (3, "autotune")])
+def test_full_batch_in_bench_launch_equals_default(recipe, how):
+    """The full batch in the launch bench.py times: the plan the autotuner picks
+    on this device (its default), or the one it picked for recipe 5 when the
+    profiles were taken (persistent queue, 16 MiB splits, variant 2). Every
+    series' result must equal, field by field, the library default plan's
+    (another kernel and work split over the same samples), and a seeded sample
+    is recomputed by the oracle."""
+    import torch
+
+    b = S.make_batch(recipe)
+    n = b.num_series
+    buf = torch.empty(b.total_elems, dtype=torch.int32, device="cuda")
+    S.fill_device(b, buf.data_ptr(), b.total_elems)
+    d = P.make_desc(b.specs["offset"], b.specs["K"], b.specs["N"])
+    dd = P.to_device(d)
+    prm = P.ks_params_init(0.05)
+    prm.max_K = int(d["K"].max())
+    out0, out1 = P.empty_results(n), P.empty_results(n)
+    with P.Context(0) as ctx:
+        P.ks_scan_batch(ctx.handle, buf, dd, n, prm, out0)
+        if how == "autotune":
+            P.ks_autotune(ctx.handle, buf, dd, n, prm, out1)
+        else:
+            P.ks_launch_set(ctx.handle, prm.max_K, n, P.KS_LAUNCH_PERSISTENT, 16 << 20, 0, variant=2)
+        out1.fill_(0xA5)
+        P.ks_scan_batch(ctx.handle, buf, dd, n, prm, out1)
+        c = P.ks_launch_get(ctx.handle, prm.max_K, n)
+        torch.cuda.synchronize()
+    print("launch", how, c.mode, c.chunk_bytes, c.graph, c.variant, flush=True)
+    g0, g1 = P.results_to_numpy(out0), P.results_to_numpy(out1)
+    for f in ("cp", "n", "m", "U", "D", "lambda", "p", "flags"):
+        assert np.array_equal(g0[f], g1[f]), f
+    rng = np.random.default_rng(100 + recipe)
+    for t in np.sort(rng.choice(n, size=4, replace=False)):
+        o0, k, nn_ = int(d[t]["offset"]), int(d[t]["K"]), int(d[t]["N"])
+        r = buf[o0:o0 + k * nn_].cpu().numpy().view(np.uint32).reshape(k, nn_)
+        o = O.scan_series(r)
+        assert (g1[t]["cp"], g1[t]["U"], g1[t]["n"], g1[t]["m"]) == (o["cp"], o["U"], o["n"], o["m"]), t
+        assert g1[t]["D"] == o["D"] and g1[t]["lambda"] == o["lambda"]
+        assert bool(g1[t]["flags"] & P.KS_SIGNIFICANT) == bool(o["significant"])
+        assert g1[t]["p"] == o["p"] or abs(g1[t]["p"] - o["p"]) <= 1e-12 * abs(o["p"]), t
+    del buf
+    torch.cuda.empty_cache()
