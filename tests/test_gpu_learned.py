@@ -61,6 +61,32 @@ def test_features_bit_exact(ctx, recipe, num):
         assert np.array_equal(f[a:a + len(ref)], ref), t
 
 
+@pytest.mark.parametrize("recipe,count", [(3, 24), (5, 6)])
+def test_features_full_size_sampled(ctx, recipe, count):
+    """The whole batch of a recipe (recipe 5: 64 GiB, what the bench's learned
+    leg reads) in one call: every feature finite, a seeded sample of series
+    bit-equal to the oracle's."""
+    import torch
+
+    b = S.make_batch(recipe)
+    buf = torch.empty(b.total_elems, dtype=torch.int32, device="cuda")
+    S.fill_device(b, buf.data_ptr(), b.total_elems)
+    d = P.make_desc(b.specs["offset"], b.specs["K"], b.specs["N"])
+    rows = int(d["K"].astype(np.int64).sum())
+    feats = torch.full((rows * 9,), float("nan"), dtype=torch.float32, device="cuda")
+    P.ks_features(ctx.handle, buf, P.to_device(d), len(d), int(d["K"].max()), feats)
+    torch.cuda.synchronize()
+    f = feats.cpu().numpy().reshape(rows, 9)
+    assert np.isfinite(f).all() and (f >= 0).all()
+    rng = np.random.default_rng(40 + recipe)
+    for t in rng.choice(len(d), count, replace=False):
+        o, a, k, n = int(d[t]["offset"]), int(d[t]["aux_offset"]), int(d[t]["K"]), int(d[t]["N"])
+        ref = O.features(buf[o:o + k * n].cpu().numpy().view(np.uint32).reshape(k, n))
+        assert np.array_equal(f[a:a + k], ref), int(t)
+    del buf, feats
+    torch.cuda.empty_cache()
+
+
 def test_learn_reserve_then_features():
     """A reserved workspace (fresh context, reserved before any learned call, then a smaller and a
     training reservation) serves the feature pass, which stays bit-exact; bad sizes are rejected."""
