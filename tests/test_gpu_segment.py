@@ -200,3 +200,33 @@ def test_segment_full_size_recipe2_sampled(ctx):
         o = int(d[t]["offset"])
         r = buf[o:o + 256 * 1024].cpu().numpy().view(np.uint32).reshape(256, 1024)
         check_series(cps[t], int(counts[t]), O.segment(r), int(t))
+
+
+@pytest.mark.parametrize("recipe,count", [(3, 24), (5, 6)])
+def test_segment_full_size_sampled(ctx, recipe, count):
+    """The whole batch as the bench's segmentation leg runs it (64 boundaries
+    at most per series; recipe 5: 64 GiB): every series' boundaries sorted,
+    distinct and inside their series, a seeded sample against the oracle's
+    recursion."""
+    import torch
+
+    b = S.make_batch(recipe)
+    n = b.num_series
+    buf = torch.empty(b.total_elems, dtype=torch.int32, device="cuda")
+    S.fill_device(b, buf.data_ptr(), b.total_elems)
+    d = P.make_desc(b.specs["offset"], b.specs["K"], b.specs["N"])
+    cps, counts = run(ctx, None, d, int(d["K"].max()), max_cp=64, x_dev=buf)
+    assert np.all(counts <= 64)
+    Ks = d["K"].astype(np.int64)
+    for t in range(n):
+        v = cps[t][:counts[t]]
+        cp = v["cp"].astype(np.int64)
+        assert np.all(np.diff(cp) > 0) and np.all((cp >= 1) & (cp <= Ks[t] - 1)), t
+        assert np.all(cp - v["n"] >= 0) and np.all(cp + v["m"] <= Ks[t]), t
+    rng = np.random.default_rng(20 + recipe)
+    for t in rng.choice(n, count, replace=False):
+        o, k, nn_ = int(d[t]["offset"]), int(d[t]["K"]), int(d[t]["N"])
+        r = buf[o:o + k * nn_].cpu().numpy().view(np.uint32).reshape(k, nn_)
+        check_series(cps[t], int(counts[t]), O.segment(r), int(t))
+    del buf
+    torch.cuda.empty_cache()
