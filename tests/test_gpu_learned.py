@@ -536,3 +536,69 @@ def test_trained_network_beats_the_method_without_it(ctx, recipe, model, count, 
     torch.cuda.synchronize()
     assert np.array_equal(tp.cpu().numpy(), T.trivial_proposal(f.cpu().numpy().reshape(-1, 9), d))
     assert np.all(tc.cpu().numpy() == 1.0)
+
+
+@pytest.mark.parametrize("recipe,model", [(5, "proposal_r5"), (3, "proposal_r3")])
+def test_learned_step_full_size(ctx, recipe, model):
+    """The bench's learned leg on the whole batch (recipe 5: 8192 series, 64 GiB):
+    the trained network, w = 8 and its calibrated tau. Every FALLBACK series
+    equals the plain scan's result; every REFINED series' choice is the most
+    significant candidate within +-w of the proposal under the scan's U_c
+    (exact integer comparison, ties to the smaller c); the REFINED / FALLBACK
+    split follows confidence >= tau; a seeded sample is recomputed by the
+    oracle (scan and windowed refine)."""
+    import json
+
+    import torch
+
+    b = S.make_batch(recipe)
+    n = b.num_series
+    buf = torch.empty(b.total_elems, dtype=torch.int32, device="cuda")
+    S.fill_device(b, buf.data_ptr(), b.total_elems)
+    d = P.make_desc(b.specs["offset"], b.specs["K"], b.specs["N"])
+    d_d = P.to_device(d)
+    Ks = d["K"].astype(np.int64)
+    aux = d["aux_offset"].astype(np.int64)
+    prm = P.ks_params_init(0.05)
+    prm.max_K = int(Ks.max())
+    plain, learned = P.empty_results(n), P.empty_results(n)
+    allU_d = torch.zeros(int(Ks.sum()), dtype=torch.int32, device="cuda")
+    P.ks_scan_batch(ctx.handle, buf, d_d, n, prm, plain, all_U=allU_d)
+    rep = json.loads((P_MODELS / (model + ".json")).read_text())
+    prm.w, prm.tau = 8, float(rep["tau"])
+    prop = torch.empty(n, dtype=torch.int32, device="cuda")
+    conf = torch.empty(n, dtype=torch.float32, device="cuda")
+    with P.Model(ctx, seed=0) as m:
+        P.ks_model_load(m.handle, P_MODELS / (model + ".ckpt"))
+        P.ks_propose(ctx.handle, m.handle, buf, d_d, n, prm, prop, conf)
+        P.ks_refine(ctx.handle, d_d, n, b.total_elems, prop, conf, prm, learned)
+        torch.cuda.synchronize()
+    g0, g = P.results_to_numpy(plain), P.results_to_numpy(learned)
+    allU = allU_d.cpu().numpy().view(np.uint32).astype(np.int64)
+    pg, cg = prop.cpu().numpy().astype(np.int64), conf.cpu().numpy()
+    refined = (g["flags"] & P.KS_REFINED) != 0
+    fallback = (g["flags"] & P.KS_FALLBACK) != 0
+    assert np.all(refined ^ fallback)
+    lo, hi = np.maximum(1, pg - 8), np.minimum(Ks - 1, pg + 8)
+    want_refined = (cg >= np.float32(prm.tau)) & (lo <= hi)
+    assert np.array_equal(refined, want_refined)
+    for f in ("cp", "n", "m", "U", "D", "lambda", "p"):
+        assert np.array_equal(g[f][fallback], g0[f][fallback]), f
+    assert 0 < refined.sum() < n
+    for t in np.nonzero(refined)[0]:
+        K, c = int(Ks[t]), np.arange(lo[t], hi[t] + 1)
+        U = allU[aux[t] + c]
+        num, den = U * U, c * (K - c)
+        bi = int(g[t]["cp"]) - int(lo[t])
+        assert 0 <= bi < len(c) and int(g[t]["U"]) == int(U[bi]), t
+        assert np.all(num * den[bi] <= num[bi] * den) and np.all(num[:bi] * den[bi] < num[bi] * den[:bi]), t
+    rng = np.random.default_rng(60 + recipe)
+    for t in rng.choice(n, 4, replace=False):
+        o, k, nn_ = int(d[t]["offset"]), int(Ks[t]), int(d[t]["N"])
+        res, U = O.scan_series(buf[o:o + k * nn_].cpu().numpy().view(np.uint32).reshape(k, nn_), want_allU=True)
+        assert np.array_equal(allU[aux[t]:aux[t] + k], np.asarray(U, np.int64)), t
+        r = O.refine(U, k, int(pg[t]), float(cg[t]), 8, prm.tau)
+        assert (g[t]["cp"], g[t]["U"], g[t]["n"], g[t]["m"]) == (r["cp"], r["U"], r["n"], r["m"]), t
+        assert bool(refined[t]) == r["refined"], t
+    del buf
+    torch.cuda.empty_cache()
