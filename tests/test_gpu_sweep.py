@@ -107,33 +107,40 @@ def test_check_constructed_sweeps(ctx):
     assert int(g[-1]["disturbed"]) == 1
 
 
-def test_check_full_size_recipe2_sampled(ctx):
-    """The benchmark batch, 4096 x 256 x 1024: 24 sampled sweeps against the oracle."""
+@pytest.mark.parametrize("recipe,count", [(2, 24), (3, 24), (5, 8)])
+def test_check_full_size_sampled(ctx, recipe, count):
+    """The whole batch as the bench's check leg runs it (recipe 5: 8192 sweeps of
+    1024 steps, 64 GiB): no sweep flagged invalid, a seeded sample of sweeps
+    against the oracle's scan, per-step p50 and check."""
     import torch
 
-    b = S.make_batch(2)
+    b = S.make_batch(recipe)
     n = b.num_series
     buf = torch.empty(b.total_elems, dtype=torch.int32, device="cuda")
     S.fill_device(b, buf.data_ptr(), b.total_elems)
     d = P.make_desc(b.specs["offset"], b.specs["K"], b.specs["N"])
     dd = P.to_device(d)
+    max_K = int(d["K"].max())
+    rows = int(d["K"].astype(np.int64).sum())
     res = P.empty_results(n)
     prm = P.ks_params_init(0.05)
-    prm.max_K = 256
+    prm.max_K = max_K
     P.ks_scan_batch(ctx.handle, buf, dd, n, prm, res)
-    stats = torch.zeros(n * 256 * 32, dtype=torch.uint8, device="cuda")
-    P.ks_stats_batch(ctx.handle, buf, dd, n, 256, stats)
+    stats = torch.zeros(rows * 32, dtype=torch.uint8, device="cuda")
+    P.ks_stats_batch(ctx.handle, buf, dd, n, max_K, stats)
     out = torch.zeros(n * 32, dtype=torch.uint8, device="cuda")
-    P.ks_check_batch(ctx.handle, dd, n, 256, res, stats, out)
+    P.ks_check_batch(ctx.handle, dd, n, max_K, res, stats, out)
     torch.cuda.synchronize()
     g = out.cpu().numpy().view(P.CHECK_DTYPE)
     assert not np.any(g["flags"] & P.KS_CHECK_INVALID)
-    rng = np.random.default_rng(4)
-    for t in rng.choice(n, 24, replace=False):
-        o = int(d[t]["offset"])
-        r = buf[o:o + 256 * 1024].cpu().numpy().view(np.uint32).reshape(256, 1024)
+    rng = np.random.default_rng(4 + recipe)
+    for t in rng.choice(n, count, replace=False):
+        o, k, nn_ = int(d[t]["offset"]), int(d[t]["K"]), int(d[t]["N"])
+        r = buf[o:o + k * nn_].cpu().numpy().view(np.uint32).reshape(k, nn_)
         res_o = O.scan_series(r)
         assert_check(g[t], O.check_sweep(O.row_stats(r)["p50"], int(res_o["cp"]), bool(res_o["significant"])), t)
+    del buf
+    torch.cuda.empty_cache()
 
 
 def test_check_invalid_inputs(ctx):
