@@ -46,7 +46,7 @@ struct FeatStage {
 // load batches held in registers, kStreamed, or kGrouped) takes the t-th
 // series of that class in the plan's order (the NB = 1 launch also marks
 // malformed series with K = 0). One wave per row (four per step for kGrouped);
-// wave w takes rows [w B, (w + 1) B) with B = ceil(K / 4). Writes per row
+// wave w of W takes rows [w B, (w + 1) B) with B = ceil(K / W). Writes per row
 // the deciles (as raw samples, at row slot s * SR + 2 + i of feat_ws) and the
 // refine workspace's moments, and per series its minimum and K.
 template <int NB, int NT>

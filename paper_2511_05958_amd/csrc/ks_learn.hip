@@ -369,7 +369,8 @@ int ks_features(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
                      max_K, plan);
   hipLaunchKernelGGL((ks::features_kernel<1, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
                      num_series, max_K, SR, learn_ws(ctx), b.feat, plan);
-  hipLaunchKernelGGL((ks::features_kernel<2, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
+  hipLaunchKernelGGL((ks::features_kernel<2, ks::row_pass_threads(2)>), dim3(num_series),
+                     dim3(ks::row_pass_threads(2)), 0, st, samples, num_samples, desc,
                      num_series, max_K, SR, learn_ws(ctx), b.feat, plan);
   hipLaunchKernelGGL((ks::features_kernel<4, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
                      num_series, max_K, SR, learn_ws(ctx), b.feat, plan);

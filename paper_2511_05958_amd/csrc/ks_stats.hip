@@ -43,11 +43,11 @@ __device__ double u128_to_double(u128 v) {
 }
 
 template <int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_waves_per_eu(NB)))) void row_stats_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
+__global__ __launch_bounds__(ks::row_pass_threads(NB)) __attribute__((amdgpu_waves_per_eu(ks::stats_waves_per_eu(NB)))) void row_stats_kernel(const uint32_t* __restrict__ samples, uint64_t num_samples,
                                                         const ks_desc* __restrict__ desc, uint32_t num_series,
                                                         uint32_t max_K, ks_row_stats* __restrict__ out,
                                                         uint64_t out_rows, const uint32_t* __restrict__ plan) {
-  constexpr int W = 4;
+  constexpr int W = ks::row_pass_threads(NB) / ks::kWave;
   // rows per contiguous write of a wave's records (64 for rows of two or more
   // load batches: fewer, longer write bursts among the reads)
   constexpr uint32_t kStage = NB == 1 || NB == (int)ks::kGrouped ? 16u : 64u;
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ks::stats_w
   if (!fits) return;
   ks_row_stats* o = out + d.aux_offset;
   if (bad) {
-    for (uint32_t i = threadIdx.x; i < d.K; i += 256) o[i] = ks_row_stats{NAN, NAN, 0u, 0u, 0u, 0u};
+    for (uint32_t i = threadIdx.x; i < d.K; i += (uint32_t)ks::row_pass_threads(NB)) o[i] = ks_row_stats{NAN, NAN, 0u, 0u, 0u, 0u};
     return;
   }
   const uint32_t K = d.K, N = d.N;
@@ -170,15 +170,15 @@ extern "C" int ks_stats_batch(ks_ctx* ctx, const uint32_t* samples, uint64_t num
   uint32_t* plan = reinterpret_cast<uint32_t*>(ctx->items);
   hipLaunchKernelGGL(ks::feature_plan_kernel, dim3(1), dim3(ks::kFeatPlanNT), 0, st, desc, num_series, num_samples,
                      max_K, plan);
-  hipLaunchKernelGGL(row_stats_kernel<1>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
+  hipLaunchKernelGGL(row_stats_kernel<1>, dim3(num_series), dim3(ks::row_pass_threads(1)), 0, st, samples, num_samples, desc, num_series,
                      max_K, out, out_rows, (const uint32_t*)plan);
-  hipLaunchKernelGGL(row_stats_kernel<2>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
+  hipLaunchKernelGGL(row_stats_kernel<2>, dim3(num_series), dim3(ks::row_pass_threads(2)), 0, st, samples, num_samples, desc, num_series,
                      max_K, out, out_rows, (const uint32_t*)plan);
-  hipLaunchKernelGGL(row_stats_kernel<4>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc, num_series,
+  hipLaunchKernelGGL(row_stats_kernel<4>, dim3(num_series), dim3(ks::row_pass_threads(4)), 0, st, samples, num_samples, desc, num_series,
                      max_K, out, out_rows, (const uint32_t*)plan);
-  hipLaunchKernelGGL(row_stats_kernel<ks::kStreamed>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc,
+  hipLaunchKernelGGL(row_stats_kernel<ks::kStreamed>, dim3(num_series), dim3(ks::row_pass_threads(ks::kStreamed)), 0, st, samples, num_samples, desc,
                      num_series, max_K, out, out_rows, (const uint32_t*)plan);
-  hipLaunchKernelGGL(row_stats_kernel<ks::kGrouped>, dim3(num_series), dim3(256), 0, st, samples, num_samples, desc,
+  hipLaunchKernelGGL(row_stats_kernel<ks::kGrouped>, dim3(num_series), dim3(ks::row_pass_threads(ks::kGrouped)), 0, st, samples, num_samples, desc,
                      num_series, max_K, out, out_rows, (const uint32_t*)plan);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? KS_OK : hip_fail(e, "row stats launch");
