@@ -367,16 +367,20 @@ int ks_features(ks_ctx* ctx, const uint32_t* samples, uint64_t num_samples, cons
   uint32_t* plan = reinterpret_cast<uint32_t*>(b.logits);
   hipLaunchKernelGGL(ks::feature_plan_kernel, dim3(1), dim3(ks::kFeatPlanNT), 0, st, desc, num_series, num_samples,
                      max_K, plan);
-  hipLaunchKernelGGL((ks::features_kernel<1, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
+  hipLaunchKernelGGL((ks::features_kernel<1, ks::row_pass_threads(1)>), dim3(num_series),
+                     dim3(ks::row_pass_threads(1)), 0, st, samples, num_samples, desc,
                      num_series, max_K, SR, learn_ws(ctx), b.feat, plan);
   hipLaunchKernelGGL((ks::features_kernel<2, ks::row_pass_threads(2)>), dim3(num_series),
                      dim3(ks::row_pass_threads(2)), 0, st, samples, num_samples, desc,
                      num_series, max_K, SR, learn_ws(ctx), b.feat, plan);
-  hipLaunchKernelGGL((ks::features_kernel<4, kNT>), dim3(num_series), dim3(kNT), 0, st, samples, num_samples, desc,
+  hipLaunchKernelGGL((ks::features_kernel<4, ks::row_pass_threads(4)>), dim3(num_series),
+                     dim3(ks::row_pass_threads(4)), 0, st, samples, num_samples, desc,
                      num_series, max_K, SR, learn_ws(ctx), b.feat, plan);
-  hipLaunchKernelGGL((ks::features_kernel<ks::kStreamed, kNT>), dim3(num_series), dim3(kNT), 0, st, samples,
+  hipLaunchKernelGGL((ks::features_kernel<ks::kStreamed, ks::row_pass_threads(ks::kStreamed)>), dim3(num_series),
+                     dim3(ks::row_pass_threads(ks::kStreamed)), 0, st, samples,
                      num_samples, desc, num_series, max_K, SR, learn_ws(ctx), b.feat, plan);
-  hipLaunchKernelGGL((ks::features_kernel<ks::kGrouped, kNT>), dim3(num_series), dim3(kNT), 0, st, samples,
+  hipLaunchKernelGGL((ks::features_kernel<ks::kGrouped, ks::row_pass_threads(ks::kGrouped)>), dim3(num_series),
+                     dim3(ks::row_pass_threads(ks::kGrouped)), 0, st, samples,
                      num_samples, desc, num_series, max_K, SR, learn_ws(ctx), b.feat, plan);
   hipLaunchKernelGGL((ks::feature_pack_kernel<kNT>), dim3(num_series, (SR + kNT - 1) / kNT), dim3(kNT), 0, st, desc,
                      num_series, features, feature_rows, b.x0, SR, learn_ws(ctx), b.feat);
