@@ -148,7 +148,12 @@ template <int KMAX>
 void launch_refine(const ks_desc* desc, uint32_t n, uint64_t num_samples, uint32_t max_K, const ks_params& prm,
                    const int32_t* prop, const float* conf, ks::LearnWs lw, uint32_t SR, ks_result* out,
                    hipStream_t st) {
-  hipLaunchKernelGGL((ks::refine_kernel<KMAX, kNT, kRB>), dim3(n), dim3(kNT), 0, st, desc, n, num_samples, max_K, prm,
+  // K classes of 1024 and 2048 rows in 512-thread workgroups: their LDS, not
+  // registers, limits the workgroups per CU, so twice the threads per
+  // workgroup doubles the waves walking the fallback series (the learned
+  // step on 8192 x 1024 x 2048 0.5% faster)
+  constexpr int RNT = KMAX >= 1024 ? 512 : kNT;
+  hipLaunchKernelGGL((ks::refine_kernel<KMAX, RNT, kRB>), dim3(n), dim3(RNT), 0, st, desc, n, num_samples, max_K, prm,
                      prop, conf, lw, SR, out);
 }
 
